@@ -1,0 +1,168 @@
+/*
+ * bfvm.h -- C ABI of the MI355X (gfx950) diffusion-decay library.
+ *
+ * The library advances S substrate densities on an nx x ny x nz voxel grid by
+ * the locally-one-dimensional (LOD) backward-Euler step of BioFVM-B: a bulk
+ * source/sink term, then Dirichlet overwrites interleaved with three implicit
+ * 1-D sweeps along x, y and z, each sweep solving one constant-coefficient
+ * tridiagonal system per grid line with the Thomas algorithm (paper Sec. 2,
+ * the 7-stage solver and Algorithm 1; Thomas constants of App. A), under
+ * zero-flux boundaries.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Field layout: a dense array of nz*ny*nx*nsub elements, element
+ *    ((z*ny + y)*nx + x)*nsub + s; substrate innermost, x the contiguous
+ *    spatial axis.  Element type double (BFVM_F64) or float (BFVM_F32,
+ *    BFVM_F32_FAST).
+ *  - Field pointers passed to bfvm_step / bfvm_sweep / bfvm_step_adjoint are
+ *    DEVICE pointers owned by the caller (for example a contiguous torch
+ *    tensor).  The library never frees or reallocates them.  Work is enqueued
+ *    asynchronously on the grid's HIP stream; the caller keeps the buffers
+ *    alive until that stream has finished the work.
+ *  - Arrays passed to bfvm_set_* are HOST pointers; they are copied before
+ *    the call returns and may be freed afterwards.
+ *  - Voxel indices are flat: (z*ny + y)*nx + x, in [0, nx*ny*nz).
+ *  - Units follow the paper: um, min, um^2/min, 1/min.
+ *  - Every call returns a status code and never throws.  Arguments are
+ *    validated before any device work; a call that fails validation leaves
+ *    the grid unchanged.  bfvm_last_error() gives a thread-local detail text
+ *    for the last failing call of the calling thread.
+ *  - Library-owned device memory (coefficient tables, source and Dirichlet
+ *    lists, adjoint workspace) is allocated by bfvm_set_* / the first adjoint
+ *    call and freed by bfvm_destroy.  bfvm_step allocates nothing.
+ */
+#ifndef BFVM_H
+#define BFVM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define BFVM_OK        0
+#define BFVM_EINVAL  (-1)   /* bad size, parameter, NULL pointer, unknown dtype, non-finite value */
+#define BFVM_ERANGE  (-2)   /* voxel index outside [0, nx*ny*nz) */
+#define BFVM_ESTATE  (-3)   /* call out of order (e.g. step before set_params) */
+#define BFVM_EDEVICE (-4)   /* HIP runtime error; bfvm_last_error() has hipGetErrorString text */
+#define BFVM_ENOMEM  (-5)   /* host or device allocation failed */
+
+/* ---- storage / arithmetic types ---------------------------------------- */
+#define BFVM_F64       0    /* double storage, double arithmetic, double coefficients */
+#define BFVM_F32       1    /* float storage, double in-register arithmetic, double coefficients */
+#define BFVM_F32_FAST  2    /* float storage, float arithmetic, coefficients rounded to float */
+
+typedef struct bfvm_grid_s* bfvm_grid;
+
+/* Create a grid of nx*ny*nz voxels with nsub substrates and spacings
+ * hx, hy, hz (um).  dtype is one of BFVM_F64 / BFVM_F32 / BFVM_F32_FAST.
+ * stream is a hipStream_t (NULL = the null stream) on the current device.
+ * Grid size follows the microenvironment resize of Sec. 5.3; the per-axis
+ * spacing generalises the single dx of App. A.
+ * Errors: EINVAL (n < 1, nsub < 1, h <= 0 or non-finite, bad dtype, out NULL),
+ * ENOMEM. */
+int bfvm_create(bfvm_grid* out, int64_t nx, int64_t ny, int64_t nz, int32_t nsub,
+                double hx, double hy, double hz, int32_t dtype, void* stream);
+
+/* Release all library-owned memory of g.  Synchronises g's stream first.
+ * NULL is accepted and ignored. */
+int bfvm_destroy(bfvm_grid g);
+
+/* Use another hipStream_t for subsequent work (NULL = the null stream). */
+int bfvm_set_stream(bfvm_grid g, void* stream);
+
+/* Diffusion coefficients D[nsub] (um^2/min, >= 0), decay rates
+ * lambda[nsub] (1/min, >= 0) and the time step dt (min, > 0).  Builds, in
+ * FP64 on the host, the Thomas constants of every (axis, substrate): with
+ * r = dt*D/h^2 and beta = dt*lambda/3, the diagonal 1+r+beta at the line
+ * ends and 1+2r+beta inside (1+beta for a one-voxel line), off-diagonals -r,
+ * denom_i and c'_i as in App. A (eqs. for denom and constant_c).  The decay
+ * is split into thirds over the three sweeps.
+ * Errors: EINVAL (NULL, negative or non-finite value, dt <= 0), ENOMEM, EDEVICE. */
+int bfvm_set_params(bfvm_grid g, const double* D, const double* lambda, double dt);
+
+/* Bulk source/sink cells (production and uptake by cells, Sec. 5.3).
+ * count entries; voxel[count]; secretion, saturation, uptake: [count*nsub]
+ * (entry k, substrate s at k*nsub + s).  Each step first applies, per voxel
+ * and substrate,  u <- (u + dt*sum_k S_k*rho_k) / (1 + dt*sum_k (S_k + U_k)),
+ * the implicit bulk update of BioFVM, with entries of the same voxel merged
+ * additively.  count = 0 removes all sources.  Replaces any previous list.
+ * Requires set_params (the merged terms depend on dt).
+ * Errors: EINVAL (count < 0, NULL with count > 0, negative or non-finite
+ * rates), ERANGE (voxel index), ESTATE (no params yet), ENOMEM, EDEVICE. */
+int bfvm_set_sources(bfvm_grid g, int64_t count, const int64_t* voxel,
+                     const double* secretion, const double* saturation, const double* uptake);
+
+/* Dirichlet voxels (Sec. 2: four Dirichlet applications per step, before the
+ * x, y and z sweeps and after the z sweep).  value, active: [count*nsub];
+ * entry (k, s) with active != 0 overwrites u[voxel[k], s] with value at each
+ * application; inactive entries have no effect; for repeated (voxel, s) the
+ * last active entry wins.  count = 0 removes all.  Replaces any previous list.
+ * Errors: EINVAL, ERANGE, ENOMEM, EDEVICE. */
+int bfvm_set_dirichlet(bfvm_grid g, int64_t count, const int64_t* voxel,
+                       const double* value, const uint8_t* active);
+
+/* Advance the device field by nsteps LOD steps, in place:
+ *   Src, Dir, X, Dir, Y, Dir, Z, Dir   (per step).
+ * Asynchronous on the grid's stream; allocates nothing.
+ * Errors: EINVAL (field NULL, nsteps < 0), ESTATE (no params), EDEVICE. */
+int bfvm_step(bfvm_grid g, void* field, int64_t nsteps);
+
+/* One Thomas sweep along axis (0 = x, 1 = y, 2 = z) of every line and
+ * substrate, in place, with no source or Dirichlet stage (Algorithm 1).
+ * Errors: EINVAL, ESTATE, EDEVICE. */
+int bfvm_sweep(bfvm_grid g, void* field, int32_t axis);
+
+/* Reverse of one step (not in the paper; the transpose of the step above).
+ * field_in: device field at the START of the forward step (not modified).
+ * grad: device field, on entry dL/du after the step, on exit dL/du before it.
+ * grad_D, grad_lambda: HOST [nsub], INCREMENTED by this step's dL/dD and
+ * dL/dlambda.  Recomputes the forward sweeps from field_in into a
+ * library-owned workspace of three fields (allocated on the first call),
+ * then runs Dir^T, Z^T, Dir^T, Y^T, Dir^T, X^T, Dir^T, Src^T, where each
+ * sweep transpose is a transposed Thomas solve (A = L U, solve U^T then L^T),
+ * and accumulates per substrate -y^T (L_N x) (w.r.t. r) and -y^T x (w.r.t.
+ * beta) with L_N the zero-flux Laplacian, in a fixed-order two-stage
+ * reduction (deterministic).  Synchronises the stream before returning.
+ * Errors: EINVAL, ESTATE, ENOMEM, EDEVICE. */
+int bfvm_step_adjoint(bfvm_grid g, const void* field_in, void* grad,
+                      double* grad_D, double* grad_lambda);
+
+/* Copy a device field of this grid to host memory (host_dst holds
+ * nx*ny*nz*nsub elements of the grid's storage type).  Synchronising.
+ * Errors: EINVAL, EDEVICE. */
+int bfvm_read_field(bfvm_grid g, const void* field, void* host_dst);
+
+/* Stage timing for measurement.  While enabled, every kernel launch of the
+ * grid is bracketed by HIP events on the grid's stream.  Stages: 0 source,
+ * 1 Dirichlet, 2 x sweep, 3 y sweep, 4 z sweep.  bfvm_timing_read
+ * synchronises, returns the summed milliseconds and launch count of a stage
+ * since the last reset, and bfvm_timing_reset clears them. */
+int bfvm_timing_enable(bfvm_grid g, int32_t enable);
+int bfvm_timing_read(bfvm_grid g, int32_t stage, double* total_ms, int64_t* launches);
+int bfvm_timing_reset(bfvm_grid g);
+
+/* Launch plan of a sweep axis, as chosen by the library or set by the
+ * tuner.  kind: 0 one-thread-per-line two-pass kernel, 1 register-segmented
+ * kernel with strided loads (y/z), 2 register-segmented kernel staged
+ * through LDS (x).  m: elements per thread; w: waves per workgroup;
+ * lpw: lines per wave (strided kernel) or rows per workgroup (LDS kernel).
+ * bfvm_set_plan validates the plan against the grid and returns EINVAL
+ * for one that does not fit (too few segments, LDS too large). */
+int bfvm_get_plan(bfvm_grid g, int32_t axis, int32_t* kind, int32_t* m, int32_t* w, int32_t* lpw);
+int bfvm_set_plan(bfvm_grid g, int32_t axis, int32_t kind, int32_t m, int32_t w, int32_t lpw);
+
+/* Text of a status code, and the calling thread's last error detail. */
+const char* bfvm_status_string(int status);
+const char* bfvm_last_error(void);
+
+/* Library version string. */
+const char* bfvm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BFVM_H */

@@ -67,11 +67,18 @@ def _load():
                                         _i64, _i64, _i64, _i32, _f64p, _f64p, _f64p, _dbl,
                                         _i64, _i64p, _f64p, _f64p, _f64p,
                                         _i64, _i64p, _f64p, _u8p]
+    lib.oracle_threads.argtypes = []
+    lib.oracle_threads.restype = ctypes.c_int
     for name in ("oracle_sweep", "oracle_source", "oracle_dirichlet", "oracle_step",
                  "oracle_adjoint_step"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's sweeps run on."""
+    return int(_load().oracle_threads())
 
 
 def _p(a, t=_f64p):

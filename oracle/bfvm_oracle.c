@@ -40,6 +40,7 @@
  *   - Dirichlet entries are applied in list order; an inactive entry does
  *     nothing, so the last active entry of a (voxel, substrate) wins.
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -47,6 +48,9 @@
 #define ORACLE_OK 0
 #define ORACLE_EINVAL (-1)
 #define ORACLE_ENOMEM (-5)
+
+/* Number of OpenMP threads the sweeps use (reported with CPU timings). */
+int oracle_threads(void) { return omp_get_max_threads(); }
 
 /* ---------------------------------------------------------------- O1-O3 */
 

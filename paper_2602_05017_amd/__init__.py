@@ -1,0 +1,265 @@
+"""Python binding of the gfx950 diffusion-decay library (libbfvm.so).
+
+Argument marshalling only: every stage of the LOD step (source/sink,
+Dirichlet, x/y/z Thomas sweeps, their transposes) runs in the HIP kernels
+behind the C ABI declared in ``include/bfvm.h``.  PyTorch provides device
+memory (field tensors) and streams.  There is no CPU fallback: if the library
+is not built, loading it raises.
+
+Field tensors are contiguous CUDA tensors of shape [nz, ny, nx, S] with
+dtype float64 (``"f64"``) or float32 (``"f32"``, ``"f32fast"``); element
+((z*ny + y)*nx + x)*S + s, substrate innermost (Sec. 3.1 contiguous density
+array).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbfvm.so")
+
+F64, F32, F32_FAST = 0, 1, 2
+DTYPES = {"f64": F64, "f32": F32, "f32fast": F32_FAST}
+STATUS = {0: "OK", -1: "EINVAL", -2: "ERANGE", -3: "ESTATE", -4: "EDEVICE", -5: "ENOMEM"}
+
+# every entry point declared in include/bfvm.h
+EXPORTS = [
+    "bfvm_create", "bfvm_destroy", "bfvm_set_stream", "bfvm_set_params", "bfvm_set_sources",
+    "bfvm_set_dirichlet", "bfvm_step", "bfvm_sweep", "bfvm_step_adjoint", "bfvm_read_field",
+    "bfvm_timing_enable", "bfvm_timing_read", "bfvm_timing_reset", "bfvm_get_plan", "bfvm_set_plan",
+    "bfvm_status_string", "bfvm_last_error", "bfvm_version",
+]
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_dbl = ctypes.c_double
+_f64p = ctypes.POINTER(ctypes.c_double)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+class BfvmError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str):
+        self.status = status
+        self.code = STATUS.get(status, str(status))
+        super().__init__(f"{what}: {self.code} ({detail})")
+
+
+def lib():
+    """Load libbfvm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                          f"python paper_2602_05017_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    L.bfvm_create.argtypes = [ctypes.POINTER(_vp), _i64, _i64, _i64, _i32, _dbl, _dbl, _dbl, _i32, _vp]
+    L.bfvm_destroy.argtypes = [_vp]
+    L.bfvm_set_stream.argtypes = [_vp, _vp]
+    L.bfvm_set_params.argtypes = [_vp, _f64p, _f64p, _dbl]
+    L.bfvm_set_sources.argtypes = [_vp, _i64, _i64p, _f64p, _f64p, _f64p]
+    L.bfvm_set_dirichlet.argtypes = [_vp, _i64, _i64p, _f64p, _u8p]
+    L.bfvm_step.argtypes = [_vp, _vp, _i64]
+    L.bfvm_sweep.argtypes = [_vp, _vp, _i32]
+    L.bfvm_step_adjoint.argtypes = [_vp, _vp, _vp, _f64p, _f64p]
+    L.bfvm_read_field.argtypes = [_vp, _vp, _vp]
+    L.bfvm_timing_enable.argtypes = [_vp, _i32]
+    L.bfvm_timing_read.argtypes = [_vp, _i32, _f64p, _i64p]
+    L.bfvm_timing_reset.argtypes = [_vp]
+    L.bfvm_get_plan.argtypes = [_vp, _i32, _i32p, _i32p, _i32p, _i32p]
+    L.bfvm_set_plan.argtypes = [_vp, _i32, _i32, _i32, _i32, _i32]
+    L.bfvm_status_string.argtypes = [ctypes.c_int]
+    L.bfvm_status_string.restype = ctypes.c_char_p
+    L.bfvm_last_error.argtypes = []
+    L.bfvm_last_error.restype = ctypes.c_char_p
+    L.bfvm_version.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        fn = getattr(L, name)
+        if fn.restype is ctypes.c_int or name not in ("bfvm_status_string", "bfvm_last_error", "bfvm_version"):
+            fn.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().bfvm_last_error().decode()
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise BfvmError(status, what, last_error())
+
+
+def _f64arr(a, n=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def _ptr(a, t=_f64p):
+    return a.ctypes.data_as(t) if a is not None and a.size else None
+
+
+def _current_stream():
+    import torch
+    if not torch.cuda.is_available():
+        return None    # no device: every call fails validation or reports EDEVICE
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Grid:
+    """nx*ny*nz voxels x nsub substrates, spacings h (um), storage dtype."""
+
+    def __init__(self, nx: int, ny: int, nz: int, nsub: int, h: Sequence[float] = (10.0, 10.0, 10.0),
+                 dtype: str = "f64", stream=None):
+        self.nx, self.ny, self.nz, self.nsub = int(nx), int(ny), int(nz), int(nsub)
+        self.h = tuple(float(v) for v in h)
+        if dtype not in DTYPES:
+            raise ValueError(f"dtype must be one of {list(DTYPES)}")
+        self.dtype = dtype
+        self._handle = _vp()
+        _check(lib().bfvm_create(ctypes.byref(self._handle), self.nx, self.ny, self.nz, self.nsub,
+                                 self.h[0], self.h[1], self.h[2], DTYPES[dtype],
+                                 stream if stream is not None else None), "bfvm_create")
+        self._explicit_stream = stream is not None
+
+    # -------------------------------------------------------------- helpers
+    @property
+    def handle(self):
+        return self._handle
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx, self.nsub)
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.float64 if self.dtype == "f64" else torch.float32
+
+    def _sync_stream(self):
+        if not self._explicit_stream:
+            _check(lib().bfvm_set_stream(self._handle, _current_stream()), "bfvm_set_stream")
+
+    def _field_ptr(self, t):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError("field must be a CUDA tensor")
+        if t.dtype != self.torch_dtype:
+            raise TypeError(f"field dtype {t.dtype} does not match grid dtype {self.dtype}")
+        if not t.is_contiguous() or t.numel() != self.nx * self.ny * self.nz * self.nsub:
+            raise ValueError("field must be contiguous with nz*ny*nx*nsub elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def empty_field(self):
+        import torch
+        return torch.empty(self.shape, dtype=self.torch_dtype, device="cuda")
+
+    # -------------------------------------------------------------- setup
+    def set_params(self, D, lam, dt: float):
+        D = _f64arr(D, self.nsub)
+        lam = _f64arr(lam, self.nsub)
+        self._sync_stream()
+        _check(lib().bfvm_set_params(self._handle, _ptr(D), _ptr(lam), float(dt)), "bfvm_set_params")
+
+    def set_sources(self, voxel, secretion, saturation, uptake):
+        voxel = np.ascontiguousarray(voxel, dtype=np.int64).reshape(-1)
+        n = voxel.size
+        sec = _f64arr(secretion, n * self.nsub)
+        sat = _f64arr(saturation, n * self.nsub)
+        upt = _f64arr(uptake, n * self.nsub)
+        self._sync_stream()
+        _check(lib().bfvm_set_sources(self._handle, n, _ptr(voxel, _i64p), _ptr(sec), _ptr(sat), _ptr(upt)),
+               "bfvm_set_sources")
+
+    def set_dirichlet(self, voxel, value, active):
+        voxel = np.ascontiguousarray(voxel, dtype=np.int64).reshape(-1)
+        n = voxel.size
+        val = _f64arr(value, n * self.nsub)
+        act = np.ascontiguousarray(active, dtype=np.uint8).reshape(-1)
+        if act.size != n * self.nsub:
+            raise ValueError("active must have count*nsub entries")
+        self._sync_stream()
+        _check(lib().bfvm_set_dirichlet(self._handle, n, _ptr(voxel, _i64p), _ptr(val), _ptr(act, _u8p)),
+               "bfvm_set_dirichlet")
+
+    # -------------------------------------------------------------- compute
+    def step(self, field, nsteps: int = 1):
+        p = self._field_ptr(field)
+        self._sync_stream()
+        _check(lib().bfvm_step(self._handle, p, int(nsteps)), "bfvm_step")
+        return field
+
+    def sweep(self, field, axis: int):
+        p = self._field_ptr(field)
+        self._sync_stream()
+        _check(lib().bfvm_sweep(self._handle, p, int(axis)), "bfvm_sweep")
+        return field
+
+    def step_adjoint(self, field_in, grad, grad_D=None, grad_lambda=None):
+        """One reverse step; returns (grad_D, grad_lambda) accumulators (numpy)."""
+        pin = self._field_ptr(field_in)
+        pg = self._field_ptr(grad)
+        gD = np.zeros(self.nsub) if grad_D is None else grad_D
+        gL = np.zeros(self.nsub) if grad_lambda is None else grad_lambda
+        self._sync_stream()
+        _check(lib().bfvm_step_adjoint(self._handle, pin, pg, _ptr(gD), _ptr(gL)), "bfvm_step_adjoint")
+        return gD, gL
+
+    def read_field(self, field) -> np.ndarray:
+        p = self._field_ptr(field)
+        out = np.empty(self.shape, dtype=np.float64 if self.dtype == "f64" else np.float32)
+        self._sync_stream()
+        _check(lib().bfvm_read_field(self._handle, p, out.ctypes.data_as(_vp)), "bfvm_read_field")
+        return out
+
+    # -------------------------------------------------------------- plans, timing
+    def get_plan(self, axis: int):
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(lib().bfvm_get_plan(self._handle, axis, *[ctypes.byref(x) for x in v]), "bfvm_get_plan")
+        return tuple(x.value for x in v)
+
+    def set_plan(self, axis: int, kind: int, m: int = 0, w: int = 0, lpw: int = 0):
+        _check(lib().bfvm_set_plan(self._handle, axis, kind, m, w, lpw), "bfvm_set_plan")
+
+    def timing(self, enable: bool):
+        _check(lib().bfvm_timing_enable(self._handle, 1 if enable else 0), "bfvm_timing_enable")
+
+    def timing_reset(self):
+        _check(lib().bfvm_timing_reset(self._handle), "bfvm_timing_reset")
+
+    def timing_read(self, stage: int):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(lib().bfvm_timing_read(self._handle, stage, ctypes.byref(ms), ctypes.byref(n)),
+               "bfvm_timing_read")
+        return ms.value, n.value
+
+    def close(self):
+        if self._handle:
+            lib().bfvm_destroy(self._handle)
+            self._handle = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+STAGES = {"source": 0, "dirichlet": 1, "x": 2, "y": 3, "z": 4}

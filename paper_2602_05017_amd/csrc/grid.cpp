@@ -1,0 +1,553 @@
+// C ABI of the gfx950 diffusion-decay library: grid object, FP64 coefficient
+// precompute, argument validation, step composition, adjoint step, timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace bfvm;
+
+namespace bfvm {
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace bfvm
+
+namespace {
+
+int fail(int code, const std::string& msg)
+{
+    set_error(msg);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(BFVM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                           \
+    do {                                              \
+        hipError_t _e = (expr);                       \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+template <typename P>
+void dfree(P*& p)
+{
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+template <typename P>
+int dalloc_copy(P*& dst, const P* src, size_t count, hipStream_t st)
+{
+    dfree(dst);
+    if (count == 0) return BFVM_OK;
+    hipError_t e = hipMalloc((void**)&dst, count * sizeof(P));
+    if (e != hipSuccess) {
+        dst = nullptr;
+        return fail(e == hipErrorOutOfMemory ? BFVM_ENOMEM : BFVM_EDEVICE,
+                    std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(P), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+    return BFVM_OK;
+}
+
+bool finite_nonneg(const double* a, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i]) || a[i] < 0.0) return false;
+    return true;
+}
+
+// Thomas constants of the zero-flux matrix of one (axis, substrate):
+// b_i = 1 + r + beta at both ends, 1 + 2r + beta inside, 1 + beta for n = 1,
+// off-diagonals -r; denom_1 = b_1, denom_i = b_i - r^2 / denom_{i-1}
+// (= b_i - a_i c'_{i-1} of App. A with a_i = -r, c'_{i-1} = -r / denom_{i-1}).
+// Writes invd[i*S + s] = 1 / denom_i.
+void thomas_constants(int64_t n, double r, double beta, int S, int s, double* invd)
+{
+    double prev_inv = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double diag = n == 1 ? 1.0 + beta
+                                   : ((i == 0 || i == n - 1) ? 1.0 + r + beta : 1.0 + 2.0 * r + beta);
+        const double denom = i == 0 ? diag : diag - r * r * prev_inv;
+        prev_inv = 1.0 / denom;
+        invd[i * S + s] = prev_inv;
+    }
+}
+
+int merge_sources(bfvm_grid g)
+{
+    const int S = g->S;
+    const int64_t cnt = (int64_t)g->raw_vox.size();
+    std::vector<int64_t> order(cnt);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return g->raw_vox[a] < g->raw_vox[b]; });
+    std::vector<int64_t> vox;
+    std::vector<double> P, invQ;
+    for (int64_t t = 0; t < cnt;) {
+        const int64_t v = g->raw_vox[order[t]];
+        std::vector<double> ps(S, 0.0), qs(S, 0.0);
+        for (; t < cnt && g->raw_vox[order[t]] == v; ++t) {
+            const int64_t k = order[t];
+            for (int s = 0; s < S; ++s) {
+                ps[s] += g->raw_sec[k * S + s] * g->raw_sat[k * S + s];
+                qs[s] += g->raw_sec[k * S + s] + g->raw_upt[k * S + s];
+            }
+        }
+        vox.push_back(v);
+        for (int s = 0; s < S; ++s) {
+            P.push_back(g->dt * ps[s]);
+            invQ.push_back(1.0 / (1.0 + g->dt * qs[s]));
+        }
+    }
+    int st;
+    if ((st = dalloc_copy(g->src_vox, vox.data(), vox.size(), g->stream)) != BFVM_OK) return st;
+    if ((st = dalloc_copy(g->src_P, P.data(), P.size(), g->stream)) != BFVM_OK) return st;
+    if ((st = dalloc_copy(g->src_invQ, invQ.data(), invQ.size(), g->stream)) != BFVM_OK) return st;
+    g->nsrc = (int64_t)vox.size();
+    return BFVM_OK;
+}
+
+// ---------------------------------------------------------------- timing
+void time_begin(bfvm_grid g, int stage, hipEvent_t* a)
+{
+    *a = nullptr;
+    if (!g->timing) return;
+    if (g->ev_pool.size() < 2) {
+        for (int i = 0; i < 64; ++i) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) == hipSuccess) g->ev_pool.push_back(e);
+        }
+    }
+    if (g->ev_pool.size() < 2) return;
+    *a = g->ev_pool.back();
+    g->ev_pool.pop_back();
+    (void)hipEventRecord(*a, g->stream);
+    (void)stage;
+}
+
+void time_end(bfvm_grid g, int stage, hipEvent_t a)
+{
+    if (!g->timing || !a) return;
+    hipEvent_t b = g->ev_pool.back();
+    g->ev_pool.pop_back();
+    (void)hipEventRecord(b, g->stream);
+    g->pending.push_back({stage, a, b});
+}
+
+void time_harvest(bfvm_grid g)
+{
+    if (g->pending.empty()) return;
+    (void)hipStreamSynchronize(g->stream);
+    for (auto& p : g->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            g->stage_ms[p.stage] += ms;
+            g->stage_count[p.stage] += 1;
+        }
+        g->ev_pool.push_back(p.a);
+        g->ev_pool.push_back(p.b);
+    }
+    g->pending.clear();
+}
+
+// ------------------------------------------------------------ stage runs
+int run_source(bfvm_grid g, void* u)
+{
+    if (g->nsrc == 0) return BFVM_OK;
+    hipEvent_t a;
+    time_begin(g, 0, &a);
+    hipError_t e = launch_source(g->dtype, u, g->src_vox, g->src_P, g->src_invQ, g->nsrc, g->S, g->stream);
+    time_end(g, 0, a);
+    return e == hipSuccess ? BFVM_OK : hip_fail(e, "source kernel");
+}
+
+int run_dirichlet(bfvm_grid g, void* u)
+{
+    if (g->ndir == 0) return BFVM_OK;
+    hipEvent_t a;
+    time_begin(g, 1, &a);
+    hipError_t e = launch_dirichlet(g->dtype, u, g->dir_elem, g->dir_val, g->ndir, g->stream);
+    time_end(g, 1, a);
+    return e == hipSuccess ? BFVM_OK : hip_fail(e, "dirichlet kernel");
+}
+
+int run_sweep(bfvm_grid g, int axis, const void* in, void* out, bool transposed)
+{
+    const AxisGeom geo = axis_geom(axis, g->nx, g->ny, g->nz, g->S);
+    const bool f32c = g->dtype == BFVM_F32_FAST;
+    const void* invd = f32c ? (const void*)g->invd32[axis] : (const void*)g->invd64[axis];
+    const void* r = f32c ? (const void*)g->r32[axis] : (const void*)g->r64[axis];
+    hipEvent_t a;
+    time_begin(g, 2 + axis, &a);
+    hipError_t e = launch_sweep(g->dtype, transposed, g->plan[axis], geo, in, out, invd, r, g->stream);
+    time_end(g, 2 + axis, a);
+    return e == hipSuccess ? BFVM_OK : hip_fail(e, "sweep kernel");
+}
+
+int check_grid(bfvm_grid g)
+{
+    if (!g) return fail(BFVM_EINVAL, "grid is NULL");
+    return BFVM_OK;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+
+extern "C" {
+
+const char* bfvm_version(void) { return "bfvm-gfx950 0.1"; }
+
+const char* bfvm_status_string(int status)
+{
+    switch (status) {
+        case BFVM_OK: return "ok";
+        case BFVM_EINVAL: return "invalid argument";
+        case BFVM_ERANGE: return "index out of range";
+        case BFVM_ESTATE: return "call out of order";
+        case BFVM_EDEVICE: return "HIP device error";
+        case BFVM_ENOMEM: return "out of memory";
+        default: return "unknown status";
+    }
+}
+
+const char* bfvm_last_error(void) { return g_last_error.c_str(); }
+
+int bfvm_create(bfvm_grid* out, int64_t nx, int64_t ny, int64_t nz, int32_t nsub, double hx, double hy,
+                double hz, int32_t dtype, void* stream)
+{
+    if (!out) return fail(BFVM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nz < 1) return fail(BFVM_EINVAL, "grid sizes must be >= 1");
+    if (nsub < 1) return fail(BFVM_EINVAL, "nsub must be >= 1");
+    const double h[3] = {hx, hy, hz};
+    for (double v : h)
+        if (!std::isfinite(v) || v <= 0.0) return fail(BFVM_EINVAL, "spacings must be finite and > 0");
+    if (dtype != BFVM_F64 && dtype != BFVM_F32 && dtype != BFVM_F32_FAST)
+        return fail(BFVM_EINVAL, "unknown dtype");
+    // every element index must fit in int64 and every line in the kernels' ranges
+    const double total = (double)nx * (double)ny * (double)nz * (double)nsub;
+    if (total > 9.0e18) return fail(BFVM_EINVAL, "grid too large");
+    bfvm_grid g = new (std::nothrow) bfvm_grid_s();
+    if (!g) return fail(BFVM_ENOMEM, "host allocation failed");
+    g->nx = nx;
+    g->ny = ny;
+    g->nz = nz;
+    g->S = nsub;
+    g->h[0] = hx;
+    g->h[1] = hy;
+    g->h[2] = hz;
+    g->dtype = dtype;
+    g->stream = static_cast<hipStream_t>(stream);
+    if (hipGetDevice(&g->device) != hipSuccess) g->device = 0;
+    for (int a = 0; a < 3; ++a)
+        g->plan[a] = default_plan(a, axis_geom(a, nx, ny, nz, nsub), dtype);
+    *out = g;
+    return BFVM_OK;
+}
+
+int bfvm_destroy(bfvm_grid g)
+{
+    if (!g) return BFVM_OK;
+    (void)hipStreamSynchronize(g->stream);
+    for (int a = 0; a < 3; ++a) {
+        dfree(g->invd64[a]);
+        dfree(g->r64[a]);
+        dfree(g->invd32[a]);
+        dfree(g->r32[a]);
+        if (g->work[a]) (void)hipFree(g->work[a]);
+    }
+    dfree(g->src_vox);
+    dfree(g->src_P);
+    dfree(g->src_invQ);
+    dfree(g->dir_elem);
+    dfree(g->dir_val);
+    dfree(g->red_partials);
+    dfree(g->red_out);
+    for (auto& p : g->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : g->ev_pool) (void)hipEventDestroy(e);
+    delete g;
+    return BFVM_OK;
+}
+
+int bfvm_set_stream(bfvm_grid g, void* stream)
+{
+    if (int st = check_grid(g)) return st;
+    g->stream = static_cast<hipStream_t>(stream);
+    return BFVM_OK;
+}
+
+int bfvm_set_params(bfvm_grid g, const double* D, const double* lambda, double dt)
+{
+    if (int st = check_grid(g)) return st;
+    if (!D || !lambda) return fail(BFVM_EINVAL, "D and lambda must not be NULL");
+    if (!std::isfinite(dt) || dt <= 0.0) return fail(BFVM_EINVAL, "dt must be finite and > 0");
+    if (!finite_nonneg(D, g->S)) return fail(BFVM_EINVAL, "D must be finite and >= 0");
+    if (!finite_nonneg(lambda, g->S)) return fail(BFVM_EINVAL, "lambda must be finite and >= 0");
+    const int S = g->S;
+    const int64_t ns[3] = {g->nx, g->ny, g->nz};
+    // build all tables on the host before touching device state
+    std::vector<double> invd[3], r[3];
+    std::vector<float> invd32[3], r32[3];
+    for (int a = 0; a < 3; ++a) {
+        invd[a].assign((size_t)(ns[a] * S), 0.0);
+        r[a].assign(S, 0.0);
+        for (int s = 0; s < S; ++s) {
+            r[a][s] = dt * D[s] / (g->h[a] * g->h[a]);
+            const double beta = dt * lambda[s] / 3.0;
+            thomas_constants(ns[a], r[a][s], beta, S, s, invd[a].data());
+        }
+        invd32[a].assign(invd[a].begin(), invd[a].end());
+        r32[a].assign(r[a].begin(), r[a].end());
+    }
+    for (int a = 0; a < 3; ++a) {
+        int st;
+        if ((st = dalloc_copy(g->invd64[a], invd[a].data(), invd[a].size(), g->stream))) return st;
+        if ((st = dalloc_copy(g->r64[a], r[a].data(), r[a].size(), g->stream))) return st;
+        if ((st = dalloc_copy(g->invd32[a], invd32[a].data(), invd32[a].size(), g->stream))) return st;
+        if ((st = dalloc_copy(g->r32[a], r32[a].data(), r32[a].size(), g->stream))) return st;
+    }
+    g->D.assign(D, D + S);
+    g->lambda.assign(lambda, lambda + S);
+    g->dt = dt;
+    g->have_params = true;
+    if (!g->raw_vox.empty()) return merge_sources(g);
+    return BFVM_OK;
+}
+
+int bfvm_set_sources(bfvm_grid g, int64_t count, const int64_t* voxel, const double* secretion,
+                     const double* saturation, const double* uptake)
+{
+    if (int st = check_grid(g)) return st;
+    if (count < 0) return fail(BFVM_EINVAL, "count must be >= 0");
+    if (!g->have_params) return fail(BFVM_ESTATE, "set_params must come before set_sources");
+    if (count > 0 && (!voxel || !secretion || !saturation || !uptake))
+        return fail(BFVM_EINVAL, "source arrays must not be NULL");
+    const int S = g->S;
+    const int64_t V = g->nvox();
+    for (int64_t k = 0; k < count; ++k)
+        if (voxel[k] < 0 || voxel[k] >= V) return fail(BFVM_ERANGE, "source voxel index out of range");
+    if (count > 0 && (!finite_nonneg(secretion, count * S) || !finite_nonneg(saturation, count * S) ||
+                      !finite_nonneg(uptake, count * S)))
+        return fail(BFVM_EINVAL, "source rates must be finite and >= 0");
+    g->raw_vox.assign(voxel, voxel + count);
+    g->raw_sec.assign(secretion, secretion + count * S);
+    g->raw_sat.assign(saturation, saturation + count * S);
+    g->raw_upt.assign(uptake, uptake + count * S);
+    if (count == 0) {
+        g->nsrc = 0;
+        dfree(g->src_vox);
+        dfree(g->src_P);
+        dfree(g->src_invQ);
+        return BFVM_OK;
+    }
+    return merge_sources(g);
+}
+
+int bfvm_set_dirichlet(bfvm_grid g, int64_t count, const int64_t* voxel, const double* value,
+                       const uint8_t* active)
+{
+    if (int st = check_grid(g)) return st;
+    if (count < 0) return fail(BFVM_EINVAL, "count must be >= 0");
+    if (count > 0 && (!voxel || !value || !active)) return fail(BFVM_EINVAL, "Dirichlet arrays must not be NULL");
+    const int S = g->S;
+    const int64_t V = g->nvox();
+    for (int64_t k = 0; k < count; ++k)
+        if (voxel[k] < 0 || voxel[k] >= V) return fail(BFVM_ERANGE, "Dirichlet voxel index out of range");
+    for (int64_t i = 0; i < count * S; ++i)
+        if (active[i] && !std::isfinite(value[i])) return fail(BFVM_EINVAL, "Dirichlet values must be finite");
+    // last active entry of each (voxel, substrate) wins
+    std::vector<std::pair<int64_t, int64_t>> ent;   // (element, list position)
+    for (int64_t k = 0; k < count; ++k)
+        for (int s = 0; s < S; ++s)
+            if (active[k * S + s]) ent.push_back({voxel[k] * S + s, k * S + s});
+    std::stable_sort(ent.begin(), ent.end(),
+                     [](const std::pair<int64_t, int64_t>& a, const std::pair<int64_t, int64_t>& b) {
+                         return a.first < b.first;
+                     });
+    std::vector<int64_t> elem;
+    std::vector<double> val;
+    for (size_t i = 0; i < ent.size(); ++i) {
+        if (i + 1 < ent.size() && ent[i + 1].first == ent[i].first) continue;   // a later entry wins
+        elem.push_back(ent[i].first);
+        val.push_back(value[ent[i].second]);
+    }
+    int st;
+    if ((st = dalloc_copy(g->dir_elem, elem.data(), elem.size(), g->stream))) return st;
+    if ((st = dalloc_copy(g->dir_val, val.data(), val.size(), g->stream))) return st;
+    g->ndir = (int64_t)elem.size();
+    return BFVM_OK;
+}
+
+int bfvm_step(bfvm_grid g, void* field, int64_t nsteps)
+{
+    if (int st = check_grid(g)) return st;
+    if (!field) return fail(BFVM_EINVAL, "field is NULL");
+    if (nsteps < 0) return fail(BFVM_EINVAL, "nsteps must be >= 0");
+    if (!g->have_params) return fail(BFVM_ESTATE, "set_params must come before step");
+    for (int64_t t = 0; t < nsteps; ++t) {
+        int st;
+        if ((st = run_source(g, field))) return st;
+        for (int a = 0; a < 3; ++a) {
+            if ((st = run_dirichlet(g, field))) return st;
+            if ((st = run_sweep(g, a, field, field, false))) return st;
+        }
+        if ((st = run_dirichlet(g, field))) return st;
+    }
+    return BFVM_OK;
+}
+
+int bfvm_sweep(bfvm_grid g, void* field, int32_t axis)
+{
+    if (int st = check_grid(g)) return st;
+    if (!field) return fail(BFVM_EINVAL, "field is NULL");
+    if (axis < 0 || axis > 2) return fail(BFVM_EINVAL, "axis must be 0, 1 or 2");
+    if (!g->have_params) return fail(BFVM_ESTATE, "set_params must come before sweep");
+    return run_sweep(g, axis, field, field, false);
+}
+
+int bfvm_step_adjoint(bfvm_grid g, const void* field_in, void* grad, double* grad_D, double* grad_lambda)
+{
+    if (int st = check_grid(g)) return st;
+    if (!field_in || !grad || !grad_D || !grad_lambda) return fail(BFVM_EINVAL, "NULL pointer");
+    if (!g->have_params) return fail(BFVM_ESTATE, "set_params must come before step_adjoint");
+    const size_t bytes = (size_t)g->nelem() * dtype_size(g->dtype);
+    const int S = g->S;
+    // workspace: three sweep outputs, reduction partials and results
+    for (int a = 0; a < 3; ++a) {
+        if (!g->work[a]) {
+            hipError_t e = hipMalloc(&g->work[a], bytes);
+            if (e != hipSuccess) {
+                g->work[a] = nullptr;
+                return fail(BFVM_ENOMEM, std::string("adjoint workspace: ") + hipGetErrorString(e));
+            }
+        }
+    }
+    const int64_t nb = adjoint_reduce_blocks(g->nvox());
+    if (!g->red_partials || g->red_blocks < nb) {
+        dfree(g->red_partials);
+        HIP_TRY(hipMalloc((void**)&g->red_partials, sizeof(double) * 2 * S * nb), "hipMalloc partials");
+        g->red_blocks = nb;
+    }
+    if (!g->red_out) HIP_TRY(hipMalloc((void**)&g->red_out, sizeof(double) * 2 * S * 3), "hipMalloc red_out");
+    hipStream_t st = g->stream;
+    int rc;
+    // forward recomputation: work[a] = output of sweep a (before the following Dirichlet)
+    HIP_TRY(hipMemcpyAsync(g->work[0], field_in, bytes, hipMemcpyDeviceToDevice, st), "copy");
+    if ((rc = run_source(g, g->work[0]))) return rc;
+    if ((rc = run_dirichlet(g, g->work[0]))) return rc;
+    if ((rc = run_sweep(g, 0, g->work[0], g->work[0], false))) return rc;
+    for (int a = 1; a < 3; ++a) {
+        HIP_TRY(hipMemcpyAsync(g->work[a], g->work[a - 1], bytes, hipMemcpyDeviceToDevice, st), "copy");
+        if ((rc = run_dirichlet(g, g->work[a]))) return rc;
+        if ((rc = run_sweep(g, a, g->work[a], g->work[a], false))) return rc;
+    }
+    // reverse: Dir^T, Z^T, Dir^T, Y^T, Dir^T, X^T, Dir^T, Src^T
+    for (int a = 2; a >= 0; --a) {
+        hipError_t e = launch_mask(g->dtype, grad, g->dir_elem, g->ndir, st);
+        if (e != hipSuccess) return hip_fail(e, "mask kernel");
+        if ((rc = run_sweep(g, a, grad, grad, true))) return rc;
+        const AxisGeom geo = axis_geom(a, g->nx, g->ny, g->nz, S);
+        e = launch_adjoint_reduce(g->dtype, grad, g->work[a], geo, g->nelem(), g->red_partials, g->red_blocks,
+                                  g->red_out + 2 * S * a, st);
+        if (e != hipSuccess) return hip_fail(e, "adjoint reduction");
+    }
+    hipError_t e = launch_mask(g->dtype, grad, g->dir_elem, g->ndir, st);
+    if (e != hipSuccess) return hip_fail(e, "mask kernel");
+    e = launch_source_transpose(g->dtype, grad, g->src_vox, g->src_invQ, g->nsrc, S, st);
+    if (e != hipSuccess) return hip_fail(e, "source transpose kernel");
+    std::vector<double> red(2 * S * 3);
+    HIP_TRY(hipMemcpyAsync(red.data(), g->red_out, sizeof(double) * red.size(), hipMemcpyDeviceToHost, st),
+            "copy reductions");
+    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+    // dL/dr_a = -sum y^T L_N x, dL/dbeta = -sum y^T x; dr_a/dD = dt/h_a^2, dbeta/dlambda = dt/3
+    for (int s = 0; s < S; ++s) {
+        for (int a = 0; a < 3; ++a) {
+            grad_D[s] += -red[2 * S * a + 2 * s + 0] * g->dt / (g->h[a] * g->h[a]);
+            grad_lambda[s] += -red[2 * S * a + 2 * s + 1] * g->dt / 3.0;
+        }
+    }
+    return BFVM_OK;
+}
+
+int bfvm_read_field(bfvm_grid g, const void* field, void* host_dst)
+{
+    if (int st = check_grid(g)) return st;
+    if (!field || !host_dst) return fail(BFVM_EINVAL, "NULL pointer");
+    const size_t bytes = (size_t)g->nelem() * dtype_size(g->dtype);
+    HIP_TRY(hipMemcpyAsync(host_dst, field, bytes, hipMemcpyDeviceToHost, g->stream), "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+    return BFVM_OK;
+}
+
+int bfvm_timing_enable(bfvm_grid g, int32_t enable)
+{
+    if (int st = check_grid(g)) return st;
+    if (!enable) time_harvest(g);
+    g->timing = enable != 0;
+    return BFVM_OK;
+}
+
+int bfvm_timing_read(bfvm_grid g, int32_t stage, double* total_ms, int64_t* launches)
+{
+    if (int st = check_grid(g)) return st;
+    if (stage < 0 || stage > 4 || !total_ms || !launches) return fail(BFVM_EINVAL, "bad stage or NULL");
+    time_harvest(g);
+    *total_ms = g->stage_ms[stage];
+    *launches = g->stage_count[stage];
+    return BFVM_OK;
+}
+
+int bfvm_timing_reset(bfvm_grid g)
+{
+    if (int st = check_grid(g)) return st;
+    time_harvest(g);
+    for (int i = 0; i < 5; ++i) {
+        g->stage_ms[i] = 0;
+        g->stage_count[i] = 0;
+    }
+    return BFVM_OK;
+}
+
+int bfvm_get_plan(bfvm_grid g, int32_t axis, int32_t* kind, int32_t* m, int32_t* w, int32_t* lpw)
+{
+    if (int st = check_grid(g)) return st;
+    if (axis < 0 || axis > 2 || !kind || !m || !w || !lpw) return fail(BFVM_EINVAL, "bad axis or NULL");
+    *kind = g->plan[axis].kind;
+    *m = g->plan[axis].m;
+    *w = g->plan[axis].w;
+    *lpw = g->plan[axis].lpw;
+    return BFVM_OK;
+}
+
+int bfvm_set_plan(bfvm_grid g, int32_t axis, int32_t kind, int32_t m, int32_t w, int32_t lpw)
+{
+    if (int st = check_grid(g)) return st;
+    if (axis < 0 || axis > 2) return fail(BFVM_EINVAL, "axis must be 0, 1 or 2");
+    SweepPlan p;
+    p.kind = kind;
+    p.m = m;
+    p.w = w;
+    p.lpw = lpw;
+    if (kind == PLAN_SEG_XTILE && axis != 0) return fail(BFVM_EINVAL, "the LDS tile kernel only runs the x axis");
+    const std::string why = check_plan(p, axis_geom(axis, g->nx, g->ny, g->nz, g->S), g->dtype);
+    if (!why.empty()) return fail(BFVM_EINVAL, "plan does not fit: " + why);
+    g->plan[axis] = p;
+    return BFVM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,142 @@
+// Internal declarations of the gfx950 diffusion-decay library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "bfvm.h"
+
+namespace bfvm {
+
+// Thread-local error text behind bfvm_last_error().
+void set_error(const std::string& msg);
+
+// ----------------------------------------------------------------- geometry
+//
+// A sweep along axis a sees the field as [outer][n][inner]: line (o, p) has
+// elements  o*outer_stride + p + i*stride,  i = 0..n-1, p in [0, inner),
+// and belongs to substrate p % S.
+//   x: outer = nz*ny, n = nx, inner = S,          stride = S
+//   y: outer = nz,    n = ny, inner = nx*S,       stride = nx*S
+//   z: outer = 1,     n = nz, inner = ny*nx*S,    stride = ny*nx*S
+struct AxisGeom {
+    int64_t n;
+    int64_t inner;
+    int64_t outer;
+    int64_t stride;
+    int64_t outer_stride;
+    int32_t S;
+};
+
+AxisGeom axis_geom(int axis, int64_t nx, int64_t ny, int64_t nz, int32_t S);
+
+// Launch plan of one sweep (see bfvm_get_plan in bfvm.h).
+enum PlanKind { PLAN_LINE = 0, PLAN_SEG_STRIDED = 1, PLAN_SEG_XTILE = 2 };
+
+struct SweepPlan {
+    int32_t kind = PLAN_LINE;
+    int32_t m = 0;     // elements per thread (segmented kernels)
+    int32_t w = 0;     // waves per workgroup
+    int32_t lpw = 0;   // lines per wave (strided) / rows per workgroup (x tile)
+};
+
+// Device coefficient tables of one axis: invd[i*S + s] = 1/denom_i of
+// substrate s, r[s] = dt*D_s/h_a^2.  Compute type C (double or float).
+template <typename C>
+struct Coefs {
+    const C* invd;
+    const C* r;
+};
+
+// Storage/arithmetic combinations.
+enum DType { DT_F64 = BFVM_F64, DT_F32 = BFVM_F32, DT_F32_FAST = BFVM_F32_FAST };
+
+inline size_t dtype_size(int dt) { return dt == DT_F64 ? 8 : 4; }
+
+// Validate a plan for an axis; returns empty string when it fits.
+std::string check_plan(const SweepPlan& p, const AxisGeom& g, int dtype);
+// Default plan for an axis.
+SweepPlan default_plan(int axis, const AxisGeom& g, int dtype);
+
+// Enqueue one sweep (forward Thomas, or transposed solve when transposed) of
+// field `in` into `out` (may alias) on `stream`.  coefs point to double or
+// float tables matching the dtype's compute type.
+hipError_t launch_sweep(int dtype, bool transposed, const SweepPlan& plan, const AxisGeom& g,
+                        const void* in, void* out, const void* invd, const void* r,
+                        hipStream_t stream);
+
+// Sparse stages.
+hipError_t launch_source(int dtype, void* u, const int64_t* vox, const double* P,
+                         const double* invQ, int64_t m, int32_t S, hipStream_t stream);
+hipError_t launch_source_transpose(int dtype, void* g, const int64_t* vox, const double* invQ,
+                                   int64_t m, int32_t S, hipStream_t stream);
+hipError_t launch_dirichlet(int dtype, void* u, const int64_t* elem, const double* val,
+                            int64_t cnt, hipStream_t stream);
+hipError_t launch_mask(int dtype, void* g, const int64_t* elem, int64_t cnt, hipStream_t stream);
+
+// Adjoint reduction: partials[(s*nblocks + b)*2 + {0,1}] = block b's sums of
+// y*(L_N x) and y*x over the elements of substrate s (fixed order), then
+// out[s*2 + {0,1}] = sum over b in order.  nblocks is chosen by the launcher
+// and must not exceed max_blocks.
+hipError_t launch_adjoint_reduce(int dtype, const void* y, const void* x, const AxisGeom& g,
+                                 int64_t nelem, double* partials, int64_t max_blocks,
+                                 double* out, hipStream_t stream);
+int64_t adjoint_reduce_blocks(int64_t nvox);
+
+}  // namespace bfvm
+
+// --------------------------------------------------------------- grid object
+struct bfvm_grid_s {
+    int64_t nx = 0, ny = 0, nz = 0;
+    int32_t S = 0;
+    double h[3] = {0, 0, 0};
+    int32_t dtype = BFVM_F64;
+    hipStream_t stream = nullptr;
+    int device = 0;
+
+    bool have_params = false;
+    double dt = 0.0;
+    std::vector<double> D, lambda;
+
+    // coefficient tables per axis (device): double and float copies
+    double* invd64[3] = {nullptr, nullptr, nullptr};
+    double* r64[3] = {nullptr, nullptr, nullptr};
+    float* invd32[3] = {nullptr, nullptr, nullptr};
+    float* r32[3] = {nullptr, nullptr, nullptr};
+
+    // merged sources (device)
+    int64_t nsrc = 0;
+    int64_t* src_vox = nullptr;
+    double* src_P = nullptr;
+    double* src_invQ = nullptr;
+    // raw source list (host copy, re-merged when dt changes)
+    std::vector<int64_t> raw_vox;
+    std::vector<double> raw_sec, raw_sat, raw_upt;
+
+    // Dirichlet (device), deduplicated active entries
+    int64_t ndir = 0;
+    int64_t* dir_elem = nullptr;
+    double* dir_val = nullptr;
+
+    bfvm::SweepPlan plan[3];
+
+    // adjoint workspace
+    void* work[3] = {nullptr, nullptr, nullptr};
+    double* red_partials = nullptr;
+    int64_t red_blocks = 0;
+    double* red_out = nullptr;
+
+    // stage timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    struct Pending { int stage; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    double stage_ms[5] = {0, 0, 0, 0, 0};
+    int64_t stage_count[5] = {0, 0, 0, 0, 0};
+
+    int64_t nvox() const { return nx * ny * nz; }
+    int64_t nelem() const { return nx * ny * nz * (int64_t)S; }
+};

@@ -1,0 +1,183 @@
+// Sparse stages of the LOD step and the adjoint's reductions (gfx950).
+//
+//   source      u <- (u + P) * invQ at merged source entries, with
+//               P = dt*sum S*rho and invQ = 1/(1 + dt*sum(S+U)) built in FP64
+//               on the host (production and uptake by cells, Sec. 5.3)
+//   dirichlet   u[e] <- value at active Dirichlet entries (Sec. 2, 7 stages)
+//   adjoint     transposes: mask (zero at Dirichlet entries), source
+//               (multiply by invQ), and the per-substrate sums
+//               sum y*(L_N x) and sum y*x behind dL/dD and dL/dlambda
+#include "internal.hpp"
+
+namespace bfvm {
+
+template <typename T>
+__global__ void k_source(T* u, const int64_t* __restrict__ vox, const double* __restrict__ P,
+                         const double* __restrict__ invQ, int64_t m, int S)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m * S) return;
+    const int64_t k = t / S;
+    const int s = (int)(t - k * S);
+    const int64_t e = vox[k] * S + s;
+    u[e] = (T)(((double)u[e] + P[t]) * invQ[t]);
+}
+
+template <typename T>
+__global__ void k_source_transpose(T* g, const int64_t* __restrict__ vox,
+                                   const double* __restrict__ invQ, int64_t m, int S)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m * S) return;
+    const int64_t k = t / S;
+    const int s = (int)(t - k * S);
+    const int64_t e = vox[k] * S + s;
+    g[e] = (T)((double)g[e] * invQ[t]);
+}
+
+template <typename T>
+__global__ void k_dirichlet(T* u, const int64_t* __restrict__ elem, const double* __restrict__ val,
+                            int64_t cnt)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < cnt) u[elem[t]] = (T)val[t];
+}
+
+template <typename T>
+__global__ void k_mask(T* g, const int64_t* __restrict__ elem, int64_t cnt)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < cnt) g[elem[t]] = (T)0;
+}
+
+static unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+#define DISPATCH_T(dtype, CALL)                    \
+    switch (dtype) {                               \
+        case DT_F64: { using T = double; CALL; break; } \
+        case DT_F32:                               \
+        case DT_F32_FAST: { using T = float; CALL; break; } \
+        default: return hipErrorInvalidValue;      \
+    }
+
+hipError_t launch_source(int dtype, void* u, const int64_t* vox, const double* P, const double* invQ,
+                         int64_t m, int32_t S, hipStream_t st)
+{
+    if (m == 0) return hipSuccess;
+    DISPATCH_T(dtype, hipLaunchKernelGGL(k_source<T>, dim3(blocks_for(m * S, 256)), dim3(256), 0, st,
+                                         static_cast<T*>(u), vox, P, invQ, m, S));
+    return hipGetLastError();
+}
+
+hipError_t launch_source_transpose(int dtype, void* g, const int64_t* vox, const double* invQ,
+                                   int64_t m, int32_t S, hipStream_t st)
+{
+    if (m == 0) return hipSuccess;
+    DISPATCH_T(dtype, hipLaunchKernelGGL(k_source_transpose<T>, dim3(blocks_for(m * S, 256)), dim3(256),
+                                         0, st, static_cast<T*>(g), vox, invQ, m, S));
+    return hipGetLastError();
+}
+
+hipError_t launch_dirichlet(int dtype, void* u, const int64_t* elem, const double* val, int64_t cnt,
+                            hipStream_t st)
+{
+    if (cnt == 0) return hipSuccess;
+    DISPATCH_T(dtype, hipLaunchKernelGGL(k_dirichlet<T>, dim3(blocks_for(cnt, 256)), dim3(256), 0, st,
+                                         static_cast<T*>(u), elem, val, cnt));
+    return hipGetLastError();
+}
+
+hipError_t launch_mask(int dtype, void* g, const int64_t* elem, int64_t cnt, hipStream_t st)
+{
+    if (cnt == 0) return hipSuccess;
+    DISPATCH_T(dtype, hipLaunchKernelGGL(k_mask<T>, dim3(blocks_for(cnt, 256)), dim3(256), 0, st,
+                                         static_cast<T*>(g), elem, cnt));
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ adjoint reductions
+//
+// Grid (nblocks, S).  Block b of substrate s visits voxels v = b*256 + t,
+// stepping by nblocks*256, element e = v*S + s.  Along the sweep axis the
+// element's position is i = (v / vstride) % n, where vstride is the voxel
+// stride of the axis, and (L_N x)_i = [i>0](x_i - x_{i-1}) + [i<n-1](x_i - x_{i+1}).
+// Per-thread sums are combined by a fixed-shape LDS tree, then the partials
+// of all blocks are added in block order by one thread per substrate, so the
+// result does not depend on scheduling.
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_partials(const T* __restrict__ y, const T* __restrict__ x,
+                                                      int64_t nvox, int64_t vstride, int64_t n, int S,
+                                                      double* __restrict__ partials)
+{
+    __shared__ double s0[256], s1[256];
+    const int s = blockIdx.y;
+    const int64_t nb = gridDim.x;
+    const int64_t est = vstride * S;   // element stride along the axis
+    double a0 = 0.0, a1 = 0.0;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < nvox; v += nb * 256) {
+        const int64_t i = (v / vstride) % n;
+        const int64_t e = v * S + s;
+        const double xe = (double)x[e];
+        double lx = 0.0;
+        if (i > 0) lx += xe - (double)x[e - est];
+        if (i < n - 1) lx += xe - (double)x[e + est];
+        const double ye = (double)y[e];
+        a0 += ye * lx;
+        a1 += ye * xe;
+    }
+    s0[threadIdx.x] = a0;
+    s1[threadIdx.x] = a1;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s0[threadIdx.x] += s0[threadIdx.x + w];
+            s1[threadIdx.x] += s1[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partials[((int64_t)s * nb + blockIdx.x) * 2 + 0] = s0[0];
+        partials[((int64_t)s * nb + blockIdx.x) * 2 + 1] = s1[0];
+    }
+}
+
+__global__ void k_adj_final(const double* __restrict__ partials, int64_t nb, int S,
+                            double* __restrict__ out)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    double a0 = 0.0, a1 = 0.0;
+    for (int64_t b = 0; b < nb; ++b) {
+        a0 += partials[((int64_t)s * nb + b) * 2 + 0];
+        a1 += partials[((int64_t)s * nb + b) * 2 + 1];
+    }
+    out[s * 2 + 0] = a0;
+    out[s * 2 + 1] = a1;
+}
+
+int64_t adjoint_reduce_blocks(int64_t nvox)
+{
+    int64_t b = (nvox + 255) / 256;
+    return b < 1024 ? (b < 1 ? 1 : b) : 1024;
+}
+
+hipError_t launch_adjoint_reduce(int dtype, const void* y, const void* x, const AxisGeom& g,
+                                 int64_t nelem, double* partials, int64_t max_blocks, double* out,
+                                 hipStream_t st)
+{
+    const int S = g.S;
+    const int64_t nvox = nelem / S;
+    const int64_t nb = adjoint_reduce_blocks(nvox);
+    if (nb > max_blocks) return hipErrorInvalidValue;
+    const int64_t vstride = g.stride / S;
+    DISPATCH_T(dtype, hipLaunchKernelGGL(k_adj_partials<T>, dim3((unsigned)nb, (unsigned)S), dim3(256), 0,
+                                         st, static_cast<const T*>(y), static_cast<const T*>(x), nvox,
+                                         vstride, g.n, S, partials));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_final, dim3(blocks_for(S, 64)), dim3(64), 0, st, partials, nb, S, out);
+    return hipGetLastError();
+}
+
+}  // namespace bfvm

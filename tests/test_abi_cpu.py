@@ -1,0 +1,167 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+entry point declared in include/bfvm.h, and rejects bad arguments with the
+documented status codes before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bfvm.h")
+
+bf = pytest.importorskip("paper_2602_05017_amd")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bfvm_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(bf.LIB_PATH):
+        pytest.skip("libbfvm.so not built")
+    return bf.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(bf.EXPORTS) == names
+
+
+def test_no_oracle_symbols_in_product_library(L):
+    for name in ("oracle_step", "oracle_sweep", "oracle_factor"):
+        with pytest.raises(AttributeError):
+            getattr(L, name)
+
+
+def test_status_strings(L):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert L.bfvm_status_string(code)
+    assert L.bfvm_status_string(99) == b"unknown status"
+
+
+def _create(L, nx=8, ny=9, nz=10, S=2, h=(10.0, 10.0, 10.0), dtype=0):
+    g = ctypes.c_void_p()
+    st = L.bfvm_create(ctypes.byref(g), nx, ny, nz, S, h[0], h[1], h[2], dtype, None)
+    return st, g
+
+
+@pytest.mark.parametrize("args", [dict(nx=0), dict(ny=-1), dict(nz=0), dict(S=0), dict(h=(0.0, 1.0, 1.0)),
+                                  dict(h=(1.0, float("nan"), 1.0)), dict(h=(1.0, 1.0, -2.0)), dict(dtype=7)])
+def test_create_rejects_bad_arguments(L, args):
+    st, g = _create(L, **args)
+    assert st == -1
+    assert not g.value
+    assert bf.last_error()
+
+
+def test_create_null_out(L):
+    assert L.bfvm_create(None, 4, 4, 4, 1, 1.0, 1.0, 1.0, 0, None) == -1
+
+
+def test_calls_out_of_order_and_bad_values(L):
+    st, g = _create(L)
+    assert st == 0
+    f64p = bf._f64p
+    D = np.array([1.0, 2.0])
+    lam = np.array([0.1, 0.1])
+    vox = np.array([1, 2], dtype=np.int64)
+    rates = np.ones(4)
+    # step / sweep / sources before set_params
+    assert L.bfvm_step(g, ctypes.c_void_p(16), 1) == -3
+    assert L.bfvm_sweep(g, ctypes.c_void_p(16), 0) == -3
+    assert L.bfvm_set_sources(g, 2, vox.ctypes.data_as(bf._i64p), rates.ctypes.data_as(f64p),
+                              rates.ctypes.data_as(f64p), rates.ctypes.data_as(f64p)) == -3
+    # invalid parameters are rejected before any device work
+    bad = np.array([-1.0, 2.0])
+    assert L.bfvm_set_params(g, bad.ctypes.data_as(f64p), lam.ctypes.data_as(f64p), 0.01) == -1
+    inf = np.array([1.0, np.inf])
+    assert L.bfvm_set_params(g, D.ctypes.data_as(f64p), inf.ctypes.data_as(f64p), 0.01) == -1
+    assert L.bfvm_set_params(g, D.ctypes.data_as(f64p), lam.ctypes.data_as(f64p), 0.0) == -1
+    assert L.bfvm_set_params(g, None, lam.ctypes.data_as(f64p), 0.01) == -1
+    # Dirichlet validation: range, NULL, non-finite
+    val = np.ones(4)
+    act = np.ones(4, dtype=np.uint8)
+    oob = np.array([0, 8 * 9 * 10], dtype=np.int64)
+    assert L.bfvm_set_dirichlet(g, 2, oob.ctypes.data_as(bf._i64p), val.ctypes.data_as(f64p),
+                                act.ctypes.data_as(bf._u8p)) == -2
+    neg = np.array([-1, 0], dtype=np.int64)
+    assert L.bfvm_set_dirichlet(g, 2, neg.ctypes.data_as(bf._i64p), val.ctypes.data_as(f64p),
+                                act.ctypes.data_as(bf._u8p)) == -2
+    assert L.bfvm_set_dirichlet(g, -1, None, None, None) == -1
+    assert L.bfvm_set_dirichlet(g, 2, None, None, None) == -1
+    nanv = np.array([1.0, np.nan, 1.0, 1.0])
+    assert L.bfvm_set_dirichlet(g, 2, vox.ctypes.data_as(bf._i64p), nanv.ctypes.data_as(f64p),
+                                act.ctypes.data_as(bf._u8p)) == -1
+    # NULL field, bad axis, negative steps
+    assert L.bfvm_step(g, None, 1) == -1
+    assert L.bfvm_sweep(g, ctypes.c_void_p(16), 3) == -1
+    assert L.bfvm_step(None, ctypes.c_void_p(16), 1) == -1
+    assert L.bfvm_read_field(g, None, None) == -1
+    assert L.bfvm_step_adjoint(g, None, None, None, None) == -1
+    assert L.bfvm_timing_read(g, 5, None, None) == -1
+    assert L.bfvm_destroy(g) == 0
+    assert L.bfvm_destroy(None) == 0
+
+
+def _plan(L, g, axis):
+    v = [ctypes.c_int32() for _ in range(4)]
+    assert L.bfvm_get_plan(g, axis, *[ctypes.byref(x) for x in v]) == 0
+    return tuple(x.value for x in v)
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 64, 1), (256, 256, 256, 8), (1000, 1000, 1000, 4), (1, 1, 1, 1),
+                                   (2, 3, 5, 7), (192, 24, 100, 5), (4097, 3, 3, 2), (3, 3, 5000, 1)])
+@pytest.mark.parametrize("dtype", [0, 1, 2])
+def test_default_plans_are_valid(L, shape, dtype):
+    nx, ny, nz, S = shape
+    st, g = _create(L, nx, ny, nz, S, dtype=dtype)
+    assert st == 0
+    for axis in range(3):
+        kind, m, w, lpw = _plan(L, g, axis)
+        # a plan read back must be accepted as is
+        assert L.bfvm_set_plan(g, axis, kind, m, w, lpw) == 0, (axis, kind, m, w, lpw, bf.last_error())
+        if kind == 1:
+            assert w * 64 // lpw * m >= (nx, ny, nz)[axis]
+    L.bfvm_destroy(g)
+
+
+def test_set_plan_rejects_plans_that_do_not_fit(L):
+    st, g = _create(L, 100, 100, 100, 4)
+    assert L.bfvm_set_plan(g, 1, 1, 8, 1, 16) == -1      # 4 segments x 8 < 100
+    assert L.bfvm_set_plan(g, 1, 1, 5, 4, 16) == -1      # m not supported
+    assert L.bfvm_set_plan(g, 1, 2, 8, 4, 1) == -1       # LDS tile kernel is x only
+    assert L.bfvm_set_plan(g, 0, 2, 4, 1, 1) == -1       # too few waves for 25 x 4 threads
+    assert L.bfvm_set_plan(g, 0, 9, 4, 1, 1) == -1
+    assert L.bfvm_set_plan(g, 2, 0, 0, 0, 0) == 0        # the line kernel always fits
+    L.bfvm_destroy(g)
+
+
+def test_binding_raises_with_detail(L):
+    with pytest.raises(bf.BfvmError) as ei:
+        bf.Grid(0, 4, 4, 1)
+    assert ei.value.code == "EINVAL"
+    g = bf.Grid(4, 4, 4, 2)
+    with pytest.raises(bf.BfvmError) as ei:
+        g.set_sources([1], [1, 1], [1, 1], [1, 1])
+    assert ei.value.code == "ESTATE"
+    with pytest.raises(bf.BfvmError) as ei:
+        g.set_dirichlet([64], [1, 1], [1, 1])
+    assert ei.value.code == "ERANGE"
+    g.close()
+
+
+def test_product_path_does_not_import_the_oracle():
+    import subprocess
+    import sys
+    code = ("import sys, paper_2602_05017_amd as b; b.lib(); "
+            "bad = [m for m in sys.modules if m == 'oracle' or m.startswith('oracle.')]; "
+            "assert not bad, bad")
+    subprocess.run([sys.executable, "-c", code], check=True, cwd=ROOT)

@@ -1,0 +1,92 @@
+"""Full-size checks on the 1000^3 x 4 tumour-scale grid, in the launch
+configuration the benchmark times (default plans).
+
+- DCT-II eigenmode at full size: every sampled element must match the closed
+  form u0 * prod_a mu_a^-m (a property that holds at any size).
+- One step with 1e6 source/sink voxels: the full substrate with the largest
+  D is compared element by element with the FP64 oracle (substrates do not
+  couple, so the oracle runs that substrate alone).
+- The same step with FP32 storage (FP64 arithmetic) against the oracle.
+"""
+import gc
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_helpers import make_grid, rel_err
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+N = 1000
+
+
+def _free():
+    import torch
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+def test_eigenmode_full_size_sampled():
+    import torch
+    p = workloads.config(3, with_field=False)
+    ks = (3, 1, 2)
+    m = 3
+    dev = "cuda"
+    cx = torch.cos(np.pi * ks[0] * (torch.arange(N, dtype=torch.float64, device=dev) + 0.5) / N)
+    cy = torch.cos(np.pi * ks[1] * (torch.arange(N, dtype=torch.float64, device=dev) + 0.5) / N)
+    cz = torch.cos(np.pi * ks[2] * (torch.arange(N, dtype=torch.float64, device=dev) + 0.5) / N)
+    u = (cz[:, None, None, None] * cy[None, :, None, None] * cx[None, None, :, None]).expand(N, N, N, p.S)
+    u = u.contiguous()
+    p.src = None
+    g = make_grid(p)
+    g.step(u, m)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    cnt = 1_000_000
+    idx = rng.integers(0, N, (cnt, 3))
+    s = rng.integers(0, p.S, cnt)
+    it = torch.from_numpy(idx).to(dev)
+    got = u[it[:, 2], it[:, 1], it[:, 0], torch.from_numpy(s).to(dev)].cpu().numpy()
+    g.close()
+    del u
+    _free()
+    base = (np.cos(np.pi * ks[0] * (idx[:, 0] + 0.5) / N) * np.cos(np.pi * ks[1] * (idx[:, 1] + 0.5) / N)
+            * np.cos(np.pi * ks[2] * (idx[:, 2] + 0.5) / N))
+    fac = np.ones(p.S)
+    for a, k in enumerate(ks):
+        r = p.dt * p.D / p.h[a] ** 2
+        beta = p.dt * p.lam / 3.0
+        fac *= (1.0 + beta + 4.0 * r * np.sin(np.pi * k / (2.0 * N)) ** 2) ** (-m)
+    ref = base * fac[s]
+    err = np.max(np.abs(got - ref))
+    print(f"eigenmode 1000^3x4, {m} steps: max abs err {err:.3e}")
+    assert err <= 1e-12
+
+
+def _one_substrate_reference(p, s):
+    u = np.ascontiguousarray(p.u0[..., s:s + 1])
+    src = oracle.Sources(p.src.voxel, p.src.secretion[:, s:s + 1], p.src.saturation[:, s:s + 1],
+                         p.src.uptake[:, s:s + 1])
+    oracle.step(u, p.h, p.D[s:s + 1], p.lam[s:s + 1], p.dt, src, None, 1)
+    return u
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_tumour_scale_one_step_vs_oracle(dtype, tol):
+    import torch
+    p = workloads.config(3, nsteps=1)
+    s = int(np.argmax(p.D))               # the substrate with the largest r
+    g = make_grid(p, dtype)
+    u = torch.from_numpy(p.u0).to(device="cuda", dtype=g.torch_dtype)
+    g.step(u, 1)
+    torch.cuda.synchronize()
+    got = u[..., s].cpu().numpy()
+    g.close()
+    del u
+    _free()
+    ref = _one_substrate_reference(p, s)[..., 0]
+    emax, e2 = rel_err(got[..., None], ref[..., None])
+    print(f"1000^3x4 {dtype}, substrate {s} (D={p.D[s]:.3g}), 1 step: e_max={emax:.3e} e_2={e2:.3e}")
+    assert emax <= tol
