@@ -28,8 +28,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBPS = 8000.0
 STAGES = ["source", "dirichlet", "sweep_x", "sweep_y", "sweep_z"]
-KERNEL_NAMES = {"sweep_x": "k_sweep_seg_xtile", "sweep_y": "k_sweep_seg_strided",
-                "sweep_z": "k_sweep_seg_strided"}
+KERNEL_NAMES = {"sweep_x": "k_sweep_seg_strided<..., AX=0> (x rows as lines)",
+                "sweep_y": "k_sweep_seg_strided<..., AX=1>", "sweep_z": "k_sweep_seg_strided<..., AX=2>"}
 
 
 def log(msg):
@@ -45,7 +45,24 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-storage companion run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=1)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a 4 GiB buffer twice (reference for FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    import torch
+    n = (4 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    print(json.dumps({"calibration": "copy", "bytes_read_per_copy": 4 << 30, "bytes_written_per_copy": 4 << 30,
+                      "copies": 2, "GBps_read_plus_write": round(2 * 2 * (4 << 30) / t / 1e9, 1)}), flush=True)
 
 
 def workload(name):
@@ -136,6 +153,9 @@ def cpu_baseline(p, sample_steps):
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(no collectives, no sharding)"}))
@@ -159,7 +179,7 @@ def main():
     traffic = traffic_record(args.workload, "f64", dom)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": KERNEL_NAMES[dom] + f" ({dom})", "algorithmic_bytes_per_launch": alg_bytes,
+                "kernel": KERNEL_NAMES[dom], "algorithmic_bytes_per_launch": alg_bytes,
                 "avg_launch_ms": round(sweeps[dom]["avg_ms"], 4),
                 "step_alg_GBps": round(3 * alg_bytes / (ms_per_step * 1e-3) / 1e9, 1),
                 "stages_avg_ms": {k: round(v["avg_ms"], 4) for k, v in stages.items()}}

@@ -34,7 +34,7 @@ struct AxisGeom {
 AxisGeom axis_geom(int axis, int64_t nx, int64_t ny, int64_t nz, int32_t S);
 
 // Launch plan of one sweep (see bfvm_get_plan in bfvm.h).
-enum PlanKind { PLAN_LINE = 0, PLAN_SEG_STRIDED = 1, PLAN_SEG_XTILE = 2 };
+enum PlanKind { PLAN_LINE = 0, PLAN_SEG_STRIDED = 1, PLAN_SEG_XTILE = 2, PLAN_SEG_XROWS = 3 };
 
 struct SweepPlan {
     int32_t kind = PLAN_LINE;

@@ -95,85 +95,186 @@ __global__ __launch_bounds__(256) void k_sweep_line(const T* in, T* out, AxisGeo
 //
 // Shared by both segmented kernels.  v[0..cnt) holds the segment's inputs
 // (elements i0 .. i0+cnt-1 of line `line`, substrate s); on return it holds
-// the final solution.  sF/sG are LDS arrays of [K][nl] carry terms, indexed
-// [segment * nl + line].  Every thread of the block must call this (it
-// contains barriers); threads without a valid segment pass cnt = 0.
+// the final solution.  sc points to 4 LDS arrays of [K][nl] values (forward
+// local value, forward coefficient product, backward local value, backward
+// coefficient product), indexed [segment * nl + line].  Every thread of the
+// block must call this (it contains barriers); threads without a valid
+// segment pass cnt = 0, threads without a line pass writer = false.
+//
+// The carries are resolved by one leader thread per line (threads 0..nl-1),
+// which walks the K segments in order with all LDS loads issued ahead of
+// the dependent multiply-add chain, and leaves each segment's incoming carry
+// in place of its local value.
 
-template <typename C, int M, bool TR>
-__device__ __forceinline__ void solve_segment(C (&v)[M], int cnt, int64_t i0, int seg, int K,
-                                              int line, int nl, int s, int S, C r,
-                                              const C* __restrict__ invd, C* sF, C* sG,
-                                              bool writer)
+template <typename C>
+__device__ __forceinline__ void carry_scan(C* val, const C* prod, int K, int nl, int line, bool reverse)
 {
-    // forward pass with zero carry; G = product of the forward coefficients
-    C f = 0, G = 1;
+    C c = 0;
+    if (!reverse) {
+        int j = 0;
+        for (; j + 8 <= K; j += 8) {
+            C f[8], g[8];
 #pragma unroll
-    for (int k = 0; k < M; ++k) {
-        if (k < cnt) {
-            const int64_t i = i0 + k;
-            const C b = invd[i * S + s];
-            if (!TR) {
-                f = b * (v[k] + r * f);
-                G *= r * b;
-            } else {
-                const C a = i > 0 ? r * invd[(i - 1) * S + s] : (C)0;
-                f = v[k] + a * f;
-                G *= a;
-            }
-            v[k] = f;
+            for (int u = 0; u < 8; ++u) { f[u] = val[(j + u) * nl + line]; g[u] = prod[(j + u) * nl + line]; }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) { val[(j + u) * nl + line] = c; c = f[u] + g[u] * c; }
+        }
+        for (; j < K; ++j) {
+            const C f = val[j * nl + line], g = prod[j * nl + line];
+            val[j * nl + line] = c;
+            c = f + g * c;
+        }
+    } else {
+        int j = K - 1;
+        for (; j - 8 >= -1; j -= 8) {
+            C f[8], g[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) { f[u] = val[(j - u) * nl + line]; g[u] = prod[(j - u) * nl + line]; }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) { val[(j - u) * nl + line] = c; c = f[u] + g[u] * c; }
+        }
+        for (; j >= 0; --j) {
+            const C f = val[j * nl + line], g = prod[j * nl + line];
+            val[j * nl + line] = c;
+            c = f + g * c;
         }
     }
-    if (writer) {
-        sF[seg * nl + line] = f;
-        sG[seg * nl + line] = G;
+}
+
+// Ragged tails.  A line of n elements is covered by K segments of M; the
+// slots past the end (i >= n) are padding: their coefficient invd is 0 and
+// their input is any finite value (a clamped, in-bounds load).  With invd = 0
+// a padding slot yields exactly 0 in both passes and multiplies every carry
+// crossing it by 0, so it changes no real element, in the Thomas solve and
+// in the transposed solve alike.  Every segment therefore runs the same
+// guard-free code; only the final stores are guarded.
+
+// Coefficient accessors: coef(k) = invd of slot i0 + k of the thread's
+// segment (0 when i0 + k >= n), prev = invd of slot i0 - 1 (0 when i0 = 0).
+template <typename C>
+struct LdsCoef {        // the block's zero-padded LDS copy, [s][segment][k] layout
+    const C* p;                // &tab[s*SP + seg*MP]: the M slots are contiguous
+    C prev;
+    __device__ __forceinline__ C operator()(int k) const { return p[k]; }
+};
+
+template <typename C>
+struct GlobalCoef {     // the global [n][S] table, masked past the line end
+    const C* __restrict__ p;   // &invd[i0*S + s] (clamped into the table)
+    int S;
+    int last;                  // n - 1 - i0
+    C prev;
+    __device__ __forceinline__ C operator()(int k) const
+    {
+        return k <= last ? p[(k <= last ? k : 0) * S] : (C)0;
     }
-    __syncthreads();
-    C carry = 0;
-    for (int j = 0; j < seg; ++j) carry = sF[j * nl + line] + sG[j * nl + line] * carry;
-    // forward correction: t_i = f_i + (prod of coefficients up to i) * carry
+};
+
+template <typename C, int M>
+struct RegCoef {        // the segment's M values held in registers
+    C b[M];
+    C prev;
+    __device__ __forceinline__ C operator()(int k) const { return b[k]; }
+};
+
+// The three register phases of a segment.
+// forward pass with zero carry; G = product of the forward coefficients
+template <typename C, int M, bool TR, typename Coef>
+__device__ __forceinline__ void seg_forward(C (&v)[M], C r, const Coef& coef, C& f, C& G)
+{
+    f = 0;
+    G = 1;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const C b = coef(k);
+        if (!TR) {
+            f = b * (v[k] + r * f);
+            G *= r * b;
+        } else {
+            const C a = r * (k > 0 ? coef(k - 1) : coef.prev);
+            f = v[k] + a * f;
+            G *= a;
+        }
+        v[k] = f;
+    }
+}
+
+// forward correction t_i = f_i + (prod of coefficients up to i) * carry, then
+// the backward pass with zero carry; GB = product of alpha over the segment
+template <typename C, int M, bool TR, typename Coef>
+__device__ __forceinline__ void seg_middle(C (&v)[M], C r, const Coef& coef, C carry, C& bw, C& GB)
+{
     C c = carry;
 #pragma unroll
     for (int k = 0; k < M; ++k) {
-        if (k < cnt) {
-            const int64_t i = i0 + k;
-            const C a = !TR ? r * invd[i * S + s] : (i > 0 ? r * invd[(i - 1) * S + s] : (C)0);
-            c = a * c;
-            v[k] += c;
-        }
+        const C a = r * (!TR ? coef(k) : (k > 0 ? coef(k - 1) : coef.prev));
+        c = a * c;
+        v[k] += c;
     }
-    __syncthreads();   // all forward carries read before the arrays are reused
-    // backward pass with zero carry; GB = product of alpha over the segment
-    C bw = 0, GB = 1;
+    // Re-read the coefficients below instead of keeping all M of them live
+    // across both loops (they are cheap LDS/L1 reads; registers are not).
+    asm volatile("" ::: "memory");
+    bw = 0;
+    GB = 1;
 #pragma unroll
     for (int k = M - 1; k >= 0; --k) {
-        if (k < cnt) {
-            const int64_t i = i0 + k;
-            const C b = invd[i * S + s];
-            const C a = r * b;
-            if (!TR)
-                bw = v[k] + a * bw;
-            else
-                bw = b * (v[k] + r * bw);
-            GB *= a;
-            v[k] = bw;
-        }
+        const C b = coef(k);
+        const C a = r * b;
+        if (!TR)
+            bw = v[k] + a * bw;
+        else
+            bw = b * (v[k] + r * bw);
+        GB *= a;
+        v[k] = bw;
     }
-    if (writer) {
-        sF[seg * nl + line] = bw;
-        sG[seg * nl + line] = GB;
-    }
-    __syncthreads();
-    C X = 0;
-    for (int j = K - 1; j > seg; --j) X = sF[j * nl + line] + sG[j * nl + line] * X;
+}
+
+// backward correction x_i = b_i + (prod of alpha from i to the segment end) * X
+template <typename C, int M, typename Coef>
+__device__ __forceinline__ void seg_last(C (&v)[M], C r, const Coef& coef, C X)
+{
     C e = X;
 #pragma unroll
     for (int k = M - 1; k >= 0; --k) {
-        if (k < cnt) {
-            const int64_t i = i0 + k;
-            e = r * invd[i * S + s] * e;
-            v[k] += e;
-        }
+        e = r * coef(k) * e;
+        v[k] += e;
     }
+}
+
+// Solve one segment held in v (see the file comment).  sc points to 4 LDS
+// arrays of [K][nl] carry terms indexed [segment * nl + line].  Every thread
+// of the block calls this (it holds barriers); writer = the thread owns a
+// (segment, line) slot.
+template <typename C, int M, bool TR, typename Coef>
+__device__ __forceinline__ void solve_segment(C (&v)[M], int seg, int K, int line, int nl, C r,
+                                              const Coef& coef, C* sc, bool writer)
+{
+    C* sF = sc;
+    C* sG = sc + K * nl;
+    C* sB = sc + 2 * K * nl;
+    C* sH = sc + 3 * K * nl;
+    const int slot = seg * nl + line;
+    C f, G;
+    seg_forward<C, M, TR>(v, r, coef, f, G);
+    if (writer) {
+        sF[slot] = f;
+        sG[slot] = G;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nl) carry_scan(sF, sG, K, nl, threadIdx.x, false);
+    __syncthreads();
+    const C carry = writer ? sF[slot] : (C)0;
+    C bw, GB;
+    seg_middle<C, M, TR>(v, r, coef, carry, bw, GB);
+    if (writer) {
+        sB[slot] = bw;
+        sH[slot] = GB;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nl) carry_scan(sB, sH, K, nl, threadIdx.x, true);
+    __syncthreads();
+    const C X = writer ? sB[slot] : (C)0;
+    seg_last<C, M>(v, r, coef, X);
 }
 
 // --------------------------------------------------- kind 1 (strided, y / z)
@@ -183,68 +284,127 @@ __device__ __forceinline__ void solve_segment(C (&v)[M], int cnt, int64_t i0, in
 // wave's load of element k touches 64/lpw runs of lpw consecutive elements.
 // blockIdx.x: line tile, blockIdx.y: outer index.
 
-template <typename T, typename C, int M, bool TR>
-__global__ __launch_bounds__(1024) void k_sweep_seg_strided(const T* in, T* out, AxisGeom g,
-                                                            const C* __restrict__ invd,
-                                                            const C* __restrict__ rr, int lpw)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int K = blockDim.x / lpw;
-    C* sF = reinterpret_cast<C*>(smem);
-    C* sG = sF + K * lpw;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int line = lane % lpw;
-    const int seg = wave * (64 / lpw) + lane / lpw;
-    const int64_t p = (int64_t)blockIdx.x * lpw + line;
-    const bool valid = p < g.inner;
-    const int S = g.S;
-    const int s = valid ? (int)(p % S) : 0;
-    const int64_t i0 = (int64_t)seg * M;
-    const int64_t rem = g.n - i0;
-    const int cnt = (valid && rem > 0) ? (rem < M ? (int)rem : M) : 0;
-    const int64_t st = g.stride;
-    const int64_t base = (int64_t)blockIdx.y * g.outer_stride + p + i0 * st;
-    const C r = rr[s];
-    C v[M];
-#pragma unroll
-    for (int k = 0; k < M; ++k) v[k] = k < cnt ? (C)in[base + k * st] : (C)0;
-    solve_segment<C, M, TR>(v, cnt, i0, seg, K, line, lpw, s, S, r, invd, sF, sG, true);
-#pragma unroll
-    for (int k = 0; k < M; ++k)
-        if (k < cnt) out[base + k * st] = (T)v[k];
-}
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { using type = double2; };
+template <> struct Vec16<float> { using type = float4; };
 
-// ------------------------------------------------------- kind 2 (x, LDS tile)
-//
-// Block = R rows (one row = the nx*S contiguous elements of one (y, z)).
-// The rows are loaded into LDS with coalesced accesses in a padded layout:
-// element (i, s) of row r sits at r*RS + (i/M)*SB + (i%M)*S + s, with
-// SB = M*S + pad chosen so that the lanes of a wave (s fastest, then
-// segment) hit distinct banks.  Thread t = (r*K + j)*S + s solves segment j
-// of line (r, s) from registers, writes it back, and the block stores the
-// rows with coalesced accesses.
-
-struct FastDiv {   // q / d for q < 2^24, d < 2^16: (q * m) >> 40
+struct FastDiv {   // q / d for q * d <= 2^40: (q * m) >> 40
     uint64_t m;
     __host__ __device__ FastDiv() : m(1) {}
     __host__ __device__ explicit FastDiv(uint32_t d) : m(((1ull << 40) + d - 1) / d) {}
     __device__ __forceinline__ uint32_t div(uint32_t q) const { return (uint32_t)(((uint64_t)q * m) >> 40); }
 };
 
+// Copy the [n][S] coefficient table into LDS for K*M slots in [s][seg][k]
+// layout: slot (i, s) at s*SP + (i/M)*MP + i%M, with MP = M + 1 and SP chosen
+// by the host so that the (substrate, segment) pairs of a wave fall in
+// distinct banks; slots i >= n get 0.  A thread's M coefficients are then
+// contiguous and read with immediate offsets.
+template <typename C, int M>
+__device__ __forceinline__ void stage_table(C* tab, const C* __restrict__ invd, uint32_t n, uint32_t KM,
+                                            uint32_t S, uint32_t SP, FastDiv divS)
+{
+    constexpr int UNR = 8;
+    const uint32_t tot = KM * S;
+    const uint32_t nS = n * S;
+    for (uint32_t e0 = threadIdx.x; e0 < tot; e0 += UNR * blockDim.x) {
+        C buf[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const uint32_t e = e0 + u * blockDim.x;
+            buf[u] = e < nS ? invd[e] : (C)0;
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const uint32_t e = e0 + u * blockDim.x;
+            if (e < tot) {
+                const uint32_t i = divS.div(e);
+                const uint32_t sub = e - i * S;
+                tab[sub * SP + (i / M) * (M + 1) + (i % M)] = buf[u];
+            }
+        }
+    }
+}
+
+// AX (0, 1, 2) only names the axis in the kernel symbol, so that profiles
+// report the x, y and z sweeps separately.
+template <typename T, typename C, int M, bool TR, bool LDS_TAB, bool XROWS, int AX>
+__global__ __launch_bounds__(1024) void k_sweep_seg_strided(const T* in, T* out, AxisGeom g,
+                                                            const C* __restrict__ invd,
+                                                            const C* __restrict__ rr, int lpw, int SP,
+                                                            FastDiv divS)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int K = blockDim.x / lpw;
+    C* sc = reinterpret_cast<C*>(smem);
+    C* tab = sc + 4 * K * lpw;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int line = lane % lpw;
+    const int seg = wave * (64 / lpw) + lane / lpw;
+    const int64_t p = (int64_t)blockIdx.x * lpw + line;
+    const bool valid = p < g.inner;
+    const int64_t pa = valid ? p : g.inner - 1;          // clamped line for padding loads
+    const int S = g.S;
+    const int s = (int)(pa % S);
+    const int64_t i0 = (int64_t)seg * M;
+    const int64_t last = g.n - 1 - i0;                    // slots k > last are padding
+    const int cnt = !valid || last < 0 ? 0 : (last >= M ? M : (int)last + 1);
+    const int64_t st = g.stride;
+    // XROWS: the x axis run through this kernel; line pa is substrate pa % S of
+    // row pa / S, whose elements are S apart inside the row's n*S run
+    const int64_t line0 = XROWS ? (pa / S) * (g.n * S) + (pa % S) : (int64_t)blockIdx.y * g.outer_stride + pa;
+    const int64_t base = line0 + i0 * st;
+    C v[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) v[k] = (C)in[base + (k <= last ? k : last) * st];
+    const C r = rr[s];
+    const C prev = (TR && i0 > 0 && last >= 0) ? invd[(i0 - 1) * S + s] : (C)0;
+    if (LDS_TAB) {
+        stage_table<C, M>(tab, invd, (uint32_t)g.n, (uint32_t)(K * M), (uint32_t)S, (uint32_t)SP, divS);
+        __syncthreads();
+        LdsCoef<C> coef{tab + s * SP + seg * (M + 1), prev};
+        solve_segment<C, M, TR>(v, seg, K, line, lpw, r, coef, sc, true);
+    } else {
+        GlobalCoef<C> coef{invd + (last >= 0 ? i0 * S + s : s), S, (int)(last < M ? last : M), prev};
+        solve_segment<C, M, TR>(v, seg, K, line, lpw, r, coef, sc, true);
+    }
+    // An opaque store pointer makes the compiler recompute the M addresses
+    // here instead of keeping the load addresses live through the solve.
+    T* op = out + base;
+    asm volatile("" : "+v"(op));
+    if (cnt == M) {
+#pragma unroll
+        for (int k = 0; k < M; ++k) op[k * st] = (T)v[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < M; ++k)
+            if (k < cnt) op[k * st] = (T)v[k];
+    }
+}
+
+// ------------------------------------------------------- kind 2 (x, LDS tile)
+//
+// Block = R rows (one row = the nx*S contiguous elements of one (y, z)).
+// The rows are loaded into LDS with coalesced 16-byte accesses in a padded
+// layout: element (i, s) of row r sits at r*RS + (i/M)*SB + (i%M)*S + s, with
+// SB = M*S + pad chosen so that the lanes of a wave (s fastest, then
+// segment) hit distinct banks.  Thread t = (r*K + j)*S + s solves segment j
+// of line (r, s) from registers, writes it back, and the block stores the
+// rows with coalesced accesses.
+
 template <typename T, typename C, int M, bool TR>
-__global__ __launch_bounds__(1024) void k_sweep_seg_xtile(const T* in, T* out, AxisGeom g,
-                                                          const C* __restrict__ invd,
-                                                          const C* __restrict__ rr, int R, int K,
-                                                          int SB, uint32_t tile_bytes,
-                                                          FastDiv divL, FastDiv divMS)
+__global__ __launch_bounds__(512) void k_sweep_seg_xtile(const T* in, T* out, AxisGeom g,
+                                                         const C* __restrict__ invd,
+                                                         const C* __restrict__ rr, int R, int K,
+                                                         int SB, uint32_t tile_bytes,
+                                                         FastDiv divL, FastDiv divMS, bool vec)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     T* tile = reinterpret_cast<T*>(smem);
     const int S = g.S;
     const int nl = R * S;
-    C* sF = reinterpret_cast<C*>(smem + tile_bytes);
-    C* sG = sF + K * nl;
+    C* sc = reinterpret_cast<C*>(smem + tile_bytes);
     const uint32_t L = (uint32_t)(g.n * S);          // row length
     const uint32_t MS = (uint32_t)(M * S);
     const uint32_t RS = (uint32_t)(K * SB);           // tile row stride
@@ -254,11 +414,55 @@ __global__ __launch_bounds__(1024) void k_sweep_seg_xtile(const T* in, T* out, A
     const T* src = in + o0 * (int64_t)L;
     T* dst = out + o0 * (int64_t)L;
 
-    for (uint32_t e = threadIdx.x; e < tot; e += blockDim.x) {
-        const uint32_t rw = divL.div(e);
-        const uint32_t q = e - rw * L;
-        const uint32_t sg = divMS.div(q);
-        tile[rw * RS + sg * SB + (q - sg * MS)] = src[e];
+    // Loads are issued UNR at a time per thread so that many are in flight
+    // before the first LDS write waits for its data; indices past the end
+    // are clamped so every load stays in bounds.
+    constexpr int UNR = 8;
+    if (vec) {
+        // 16-byte chunks: a chunk never straddles a segment block (M*S, SB and
+        // L are multiples of the chunk) and both sides are 16-byte aligned
+        using V = typename Vec16<T>::type;
+        constexpr uint32_t VW = 16 / sizeof(T);
+        const V* srcv = reinterpret_cast<const V*>(src);
+        const uint32_t nch = tot / VW;
+        for (uint32_t c0 = threadIdx.x; c0 < nch; c0 += UNR * blockDim.x) {
+            V buf[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const uint32_t c = c0 + u * blockDim.x;
+                buf[u] = srcv[c < nch ? c : 0];
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const uint32_t c = c0 + u * blockDim.x;
+                if (c < nch) {
+                    const uint32_t e = c * VW;
+                    const uint32_t rw = divL.div(e);
+                    const uint32_t q = e - rw * L;
+                    const uint32_t sg = divMS.div(q);
+                    *reinterpret_cast<V*>(tile + rw * RS + sg * SB + (q - sg * MS)) = buf[u];
+                }
+            }
+        }
+    } else {
+        for (uint32_t e0 = threadIdx.x; e0 < tot; e0 += UNR * blockDim.x) {
+            T buf[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const uint32_t e = e0 + u * blockDim.x;
+                buf[u] = src[e < tot ? e : 0];
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const uint32_t e = e0 + u * blockDim.x;
+                if (e < tot) {
+                    const uint32_t rw = divL.div(e);
+                    const uint32_t q = e - rw * L;
+                    const uint32_t sg = divMS.div(q);
+                    tile[rw * RS + sg * SB + (q - sg * MS)] = buf[u];
+                }
+            }
+        }
     }
     __syncthreads();
 
@@ -266,28 +470,55 @@ __global__ __launch_bounds__(1024) void k_sweep_seg_xtile(const T* in, T* out, A
     const bool active = t < nl * K;
     const int s = t % S;
     const int j = (t / S) % K;
-    const int rw = t / (S * K);
+    const int rw = active ? t / (S * K) : 0;
     const bool valid = active && rw < nrows;
     const int64_t i0 = (int64_t)j * M;
-    const int64_t rem = g.n - i0;
-    const int cnt = (valid && rem > 0) ? (rem < M ? (int)rem : M) : 0;
+    const int64_t last = g.n - 1 - i0;                // slots k > last are padding
+    const int cnt = valid ? (last >= M ? M : (int)last + 1) : 0;
     const C r = rr[s];
-    T* my = tile + rw * RS + j * SB + s;
+    // padding slots read the segment's last real element (row 0 for threads
+    // without a row), so every LDS read below is of initialised data
+    const int rws = valid ? rw : 0;
+    T* my = tile + rws * RS + j * SB + s;
+    RegCoef<C, M> coef;
+    coef.prev = (TR && i0 > 0) ? invd[(i0 - 1) * S + s] : (C)0;
+    const C* cf = invd + i0 * S + s;
     C v[M];
 #pragma unroll
-    for (int k = 0; k < M; ++k) v[k] = k < cnt ? (C)my[k * S] : (C)0;
-    solve_segment<C, M, TR>(v, cnt, i0, j, K, active ? rw * S + s : 0, nl, s, S, r, invd, sF, sG,
-                            active);
+    for (int k = 0; k < M; ++k) {
+        coef.b[k] = k <= last ? cf[(k <= last ? k : 0) * S] : (C)0;
+        v[k] = (C)my[(k <= last ? k : last) * S];
+    }
+    solve_segment<C, M, TR>(v, j, K, active ? rw * S + s : 0, nl, r, coef, sc, active);
+    asm volatile("" : "+v"(my));
+    if (cnt == M) {
 #pragma unroll
-    for (int k = 0; k < M; ++k)
-        if (k < cnt) my[k * S] = (T)v[k];
+        for (int k = 0; k < M; ++k) my[k * S] = (T)v[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < M; ++k)
+            if (k < cnt) my[k * S] = (T)v[k];
+    }
     __syncthreads();
 
-    for (uint32_t e = threadIdx.x; e < tot; e += blockDim.x) {
-        const uint32_t rw2 = divL.div(e);
-        const uint32_t q = e - rw2 * L;
-        const uint32_t sg = divMS.div(q);
-        dst[e] = tile[rw2 * RS + sg * SB + (q - sg * MS)];
+    if (vec) {
+        using V = typename Vec16<T>::type;
+        constexpr uint32_t VW = 16 / sizeof(T);
+        V* dstv = reinterpret_cast<V*>(dst);
+        for (uint32_t c = threadIdx.x; c < tot / VW; c += blockDim.x) {
+            const uint32_t e = c * VW;
+            const uint32_t rw2 = divL.div(e);
+            const uint32_t q = e - rw2 * L;
+            const uint32_t sg = divMS.div(q);
+            dstv[c] = *reinterpret_cast<const V*>(tile + rw2 * RS + sg * SB + (q - sg * MS));
+        }
+    } else {
+        for (uint32_t e = threadIdx.x; e < tot; e += blockDim.x) {
+            const uint32_t rw2 = divL.div(e);
+            const uint32_t q = e - rw2 * L;
+            const uint32_t sg = divMS.div(q);
+            dst[e] = tile[rw2 * RS + sg * SB + (q - sg * MS)];
+        }
     }
 }
 
@@ -310,7 +541,7 @@ static size_t xtile_lds(int M, int S, int R, int K, int esize, int csize, uint32
     size_t tb = (size_t)R * K * xtile_sb(M, S, esize) * esize;
     tb = (tb + 15) & ~(size_t)15;
     if (tile_bytes) *tile_bytes = (uint32_t)tb;
-    return tb + 2 * (size_t)K * R * S * csize;
+    return tb + 4 * (size_t)K * R * S * csize;
 }
 
 static int compute_size(int dtype) { return dtype == DT_F32_FAST ? 4 : 8; }
@@ -326,7 +557,21 @@ std::string check_plan(const SweepPlan& p, const AxisGeom& g, int dtype)
         if (g.outer > 65535) return "too many outer blocks for the strided kernel";
         const int64_t K = (int64_t)p.w * 64 / p.lpw;
         if (K * p.m < g.n) return "too few segments for the line length";
-        if (2 * K * p.lpw * cs > kMaxLDS) return "LDS too large";
+        if (4 * K * p.lpw * cs > kMaxLDS) return "LDS too large";
+        return "";
+    }
+    if (p.kind == PLAN_SEG_XROWS) {
+        if (g.inner != g.S) return "the row-line kernel only runs the x axis";
+        if (p.lpw != 16 && p.lpw != 32 && p.lpw != 64) return "lpw must be 16, 32 or 64";
+        if (p.w < 1 || p.w > 16) return "w must be in [1, 16]";
+        const int64_t K = (int64_t)p.w * 64 / p.lpw;
+        if (K * p.m < g.n) return "too few segments for the line length";
+        if (ceil_div(g.outer * g.S, p.lpw) >= (1ll << 31)) return "too many lines";
+        const int period = cs == 8 ? 16 : 32;
+        const int64_t KM1 = K * (p.m + 1);
+        const int64_t SP = KM1 + (((64 / p.lpw - KM1) % period) + period) % period;
+        if ((4 * K * p.lpw + g.S * SP) * cs > kMaxLDS) return "LDS too large (coefficient table)";
+        if (K * p.m * g.S >= (1 << 24)) return "line too long";
         return "";
     }
     if (p.kind == PLAN_SEG_XTILE) {
@@ -334,9 +579,9 @@ std::string check_plan(const SweepPlan& p, const AxisGeom& g, int dtype)
         const int64_t K = ceil_div(g.n, p.m);
         if (p.lpw < 1) return "rows per block must be >= 1";
         const int64_t threads = K * g.S * p.lpw;
-        if (threads > 1024) return "more than 1024 threads per block";
+        if (threads > 512) return "more than 512 threads per block";
         if ((int64_t)p.w * 64 < threads) return "w too small for the rows";
-        if (p.w > 16) return "w must be <= 16";
+        if (p.w > 8) return "w must be <= 8";
         // FastDiv is exact while (index < 2^24) and index * divisor <= 2^40
         const int64_t L = g.n * g.S, tot = L * p.lpw;
         if (tot >= (1 << 24) || tot * L > (1ll << 40)) return "tile too long";
@@ -351,13 +596,30 @@ SweepPlan default_plan(int axis, const AxisGeom& g, int dtype)
     SweepPlan p;
     const int es = (int)dtype_size(dtype);
     if (axis == 0) {
+        // preferred: every (row, substrate) as a line of the strided kernel
+        {
+            const int pm[] = {32, 16, 8, 4};
+            const int lpw = 16, spw = 4;
+            for (int M : pm) {
+                if (M == 32 && g.n < 512) continue;
+                if (M == 16 && g.n < 128) continue;
+                if (M == 8 && g.n < 16) continue;
+                int64_t K = ceil_div(ceil_div(g.n, M), spw) * spw;
+                SweepPlan c;
+                c.kind = PLAN_SEG_XROWS;
+                c.m = M;
+                c.lpw = lpw;
+                c.w = (int)(K * lpw / 64);
+                if (check_plan(c, g, dtype).empty()) return c;
+            }
+        }
         const int big[] = {16, 8, 32, 4}, mid[] = {8, 4, 16, 32}, small[] = {4, 8, 16, 32};
         const int* ms = g.n >= 512 ? big : (g.n >= 64 ? mid : small);
         for (int mi = 0; mi < 4; ++mi) {
             const int M = ms[mi];
             const int64_t K = ceil_div(g.n, M);
             const int64_t per_row = K * g.S;
-            if (per_row > 1024) continue;
+            if (per_row > 512) continue;
             int64_t R = std::max<int64_t>(1, 256 / per_row);
             R = std::min<int64_t>(R, g.outer);
             SweepPlan c;
@@ -373,11 +635,12 @@ SweepPlan default_plan(int axis, const AxisGeom& g, int dtype)
         }
         return p;   // kind 0
     }
-    const int lpw = es == 8 ? 16 : 32;
+    const int lpw = 16;
     const int spw = 64 / lpw;
-    const int ms[] = {16, 8, 32, 4};
-    for (int M : ms) {
-        if (M == 16 && g.n < 128) continue;
+    const int big[] = {32, 16, 8, 4}, mid[] = {16, 32, 8, 4}, small[] = {8, 4, 16, 32};
+    const int* ms = g.n >= 512 ? big : (g.n >= 128 ? mid : small);
+    for (int mi = 0; mi < 4; ++mi) {
+        const int M = ms[mi];
         int64_t K = ceil_div(g.n, M);
         K = ceil_div(K, spw) * spw;
         SweepPlan c;
@@ -396,22 +659,52 @@ template <typename T, typename C, bool TR, int M>
 static hipError_t launch_seg(const SweepPlan& p, const AxisGeom& g, const T* in, T* out,
                              const C* invd, const C* r, hipStream_t st)
 {
-    if (p.kind == PLAN_SEG_STRIDED) {
+    if (p.kind == PLAN_SEG_STRIDED || p.kind == PLAN_SEG_XROWS) {
+        const bool xrows = p.kind == PLAN_SEG_XROWS;
+        AxisGeom gg = g;
+        if (xrows) {            // every (row, substrate) of the x axis is one line
+            gg.inner = g.outer * g.S;
+            gg.outer = 1;
+        }
         const int threads = p.w * 64;
         const int K = threads / p.lpw;
-        dim3 grid((unsigned)ceil_div(g.inner, p.lpw), (unsigned)g.outer);
-        size_t lds = 2 * (size_t)K * p.lpw * sizeof(C);
-        hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR>), grid, dim3(threads), lds, st, in, out,
-                           g, invd, r, p.lpw);
+        dim3 grid((unsigned)ceil_div(gg.inner, p.lpw), (unsigned)gg.outer);
+        const size_t scan = 4 * (size_t)K * p.lpw * sizeof(C);
+        // [s][seg][k] table: segment stride M + 1 (odd), substrate stride SP with
+        // SP = spw (mod bank period), so the spw segments x S substrates a wave
+        // touches at once land in distinct banks
+        const int period = sizeof(C) == 8 ? 16 : 32;
+        const int spw = 64 / p.lpw;
+        const int KM1 = K * (M + 1);
+        const int SP = KM1 + (((spw - KM1) % period) + period) % period;
+        const size_t tab = (size_t)g.S * SP * sizeof(C);
+        const int64_t KMS = (int64_t)K * M * g.S;
+        const bool lds_tab = scan + tab <= (size_t)kMaxLDS && KMS < (1 << 24) && KMS * g.S <= (1ll << 40);
+        const bool zaxis = g.outer == 1;
+        if (xrows)
+            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, true, true, 0>), grid, dim3(threads), scan + tab,
+                               st, in, out, gg, invd, r, p.lpw, SP, FastDiv((uint32_t)g.S));
+        else if (lds_tab && zaxis)
+            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, true, false, 2>), grid, dim3(threads), scan + tab,
+                               st, in, out, gg, invd, r, p.lpw, SP, FastDiv((uint32_t)g.S));
+        else if (lds_tab)
+            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, true, false, 1>), grid, dim3(threads), scan + tab,
+                               st, in, out, gg, invd, r, p.lpw, SP, FastDiv((uint32_t)g.S));
+        else
+            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, false, false, 1>), grid, dim3(threads), scan, st,
+                               in, out, gg, invd, r, p.lpw, SP, FastDiv((uint32_t)g.S));
     } else {
         const int K = (int)ceil_div(g.n, M);
         const int SB = xtile_sb(M, g.S, (int)sizeof(T));
         uint32_t tile_bytes = 0;
         size_t lds = xtile_lds(M, g.S, p.lpw, K, (int)sizeof(T), (int)sizeof(C), &tile_bytes);
         dim3 grid((unsigned)ceil_div(g.outer, p.lpw));
+        const int64_t VW = 16 / sizeof(T);
+        const bool vec = (M * g.S) % VW == 0 && SB % VW == 0 && (g.n * g.S) % VW == 0 &&
+                         (reinterpret_cast<uintptr_t>(in) % 16) == 0 && (reinterpret_cast<uintptr_t>(out) % 16) == 0;
         hipLaunchKernelGGL((k_sweep_seg_xtile<T, C, M, TR>), grid, dim3(p.w * 64), lds, st, in, out,
                            g, invd, r, p.lpw, K, SB, tile_bytes, FastDiv((uint32_t)(g.n * g.S)),
-                           FastDiv((uint32_t)(M * g.S)));
+                           FastDiv((uint32_t)(M * g.S)), vec);
     }
     return hipGetLastError();
 }

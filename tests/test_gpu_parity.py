@@ -26,10 +26,10 @@ def _plan(kind, axis, n, S, m=8, lpw=16, rows=1):
     if kind == 0:
         return (0, 0, 0, 0)
     K = math.ceil(n / m)
-    if kind == 1:
+    if kind in (1, 3):
         spw = 64 // lpw
         K = math.ceil(K / spw) * spw
-        return (1, m, K * lpw // 64, lpw)
+        return (kind, m, K * lpw // 64, lpw)
     return (2, m, math.ceil(rows * K * S / 64), rows)
 
 
@@ -84,6 +84,19 @@ def test_xtile_kernel_plans(m, rows):
     got = gpu_run(p, plans=plans)
     emax, _ = rel_err(got, ref)
     assert emax <= F64_TOL, (m, rows, emax)
+
+
+@pytest.mark.parametrize("m", [4, 8, 16, 32])
+@pytest.mark.parametrize("lpw", [16, 32, 64])
+def test_xrows_kernel_plans(m, lpw):
+    nx, ny, nz = NONCUBIC
+    S = 3
+    p = small_problem(NONCUBIC, S, seed=350 + m + lpw, nsrc=300, ndir=40, nsteps=2)
+    plans = {0: _plan(3, 0, nx, S, m=m, lpw=lpw)}
+    ref = oracle_run(p)
+    got = gpu_run(p, plans=plans)
+    emax, _ = rel_err(got, ref)
+    assert emax <= F64_TOL, (m, lpw, emax)
 
 
 def test_line_kernel_all_axes():
