@@ -106,7 +106,9 @@ def timed_run(p, dtype, steps, warmup, u_host):
     stages = {}
     for i, name in enumerate(STAGES):
         ms, n = g.timing_read(i)
-        stages[name] = {"total_ms": ms, "launches": n, "avg_ms": ms / n if n else 0.0}
+        elems = g.timing_elements(i) if name.startswith("sweep") else 0
+        stages[name] = {"total_ms": ms, "launches": n, "avg_ms": ms / n if n else 0.0,
+                        "elements_per_launch": elems / n if n else 0}
     g.timing(False)
     return g, u, t, stages
 
@@ -173,16 +175,20 @@ def main():
     value = upd_per_step * args.steps / t
     log(f"f64: {ms_per_step:.3f} ms/step, {value:.4g} updates/s")
     sweeps = {k: v for k, v in stages.items() if k.startswith("sweep")}
-    dom = max(sweeps, key=lambda k: sweeps[k]["avg_ms"])
-    alg_bytes = 2 * 8 * upd_per_step             # one read + one write per element
+    # dominant kernel: the sweep with the largest share of the step
+    dom = max(sweeps, key=lambda k: sweeps[k]["total_ms"])
+    alg_bytes = int(2 * 8 * sweeps[dom]["elements_per_launch"])   # one read + one write per element
     achieved = alg_bytes / (sweeps[dom]["avg_ms"] * 1e-3) / 1e9
     traffic = traffic_record(args.workload, "f64", dom)
+    sched = g.get_schedule()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": KERNEL_NAMES[dom], "algorithmic_bytes_per_launch": alg_bytes,
-                "avg_launch_ms": round(sweeps[dom]["avg_ms"], 4),
-                "step_alg_GBps": round(3 * alg_bytes / (ms_per_step * 1e-3) / 1e9, 1),
-                "stages_avg_ms": {k: round(v["avg_ms"], 4) for k, v in stages.items()}}
+                "avg_launch_ms": round(sweeps[dom]["avg_ms"], 5),
+                "launches_per_step": sweeps[dom]["launches"] // args.steps,
+                "step_alg_GBps": round(3 * 2 * 8 * upd_per_step / (ms_per_step * 1e-3) / 1e9, 1),
+                "schedule": {"fused_yz_slabs": sched[0] == 1, "slab_width": sched[1]},
+                "stages_ms_per_step": {k: round(v["total_ms"] / args.steps, 4) for k, v in stages.items()}}
     fp64_ref = u[..., 0].flatten()[:: 997].double().cpu() if not args.no_fp32 else None
     g.close()
     del u
@@ -193,8 +199,8 @@ def main():
         g32, u32, t32, st32 = timed_run(p, "f32", args.steps, args.warmup, u_host)
         v32 = upd_per_step * args.steps / t32
         s32 = {k: v for k, v in st32.items() if k.startswith("sweep")}
-        d32 = max(s32, key=lambda k: s32[k]["avg_ms"])
-        ach32 = 2 * 4 * upd_per_step / (s32[d32]["avg_ms"] * 1e-3) / 1e9
+        d32 = max(s32, key=lambda k: s32[k]["total_ms"])
+        ach32 = 2 * 4 * s32[d32]["elements_per_launch"] / (s32[d32]["avg_ms"] * 1e-3) / 1e9
         samp = u32[..., 0].flatten()[:: 997].double().cpu()
         err = float((samp - fp64_ref).abs().max() / fp64_ref.abs().max())
         fp32 = {"value": v32, "ms_per_step": round(1e3 * t32 / args.steps, 3),

@@ -30,7 +30,8 @@
  *    for the last failing call of the calling thread.
  *  - Library-owned device memory (coefficient tables, source and Dirichlet
  *    lists, adjoint workspace) is allocated by bfvm_set_* / the first adjoint
- *    call and freed by bfvm_destroy.  bfvm_step allocates nothing.
+ *    call and freed by bfvm_destroy.  bfvm_step and bfvm_sweep allocate
+ *    nothing.
  */
 #ifndef BFVM_H
 #define BFVM_H
@@ -144,10 +145,29 @@ int bfvm_timing_enable(bfvm_grid g, int32_t enable);
 int bfvm_timing_read(bfvm_grid g, int32_t stage, double* total_ms, int64_t* launches);
 int bfvm_timing_reset(bfvm_grid g);
 
+/* Elements swept by a stage since the last reset (sum over its launches),
+ * for per-launch byte counts: stages 2..4 only. */
+int bfvm_timing_elements(bfvm_grid g, int32_t stage, int64_t* elements);
+
+/* Step schedule.  0: the three sweeps each run over the whole field.
+ * 1: the x sweep runs over the whole field, then the y and z sweeps run back
+ * to back on x-slabs of slab_width columns, each slab's Dirichlet entries
+ * being overwritten between its y and z sweeps.  2: the x and y sweeps run
+ * back to back on z-slabs of slab_width planes, then the z sweep runs over
+ * the whole field.  The lines of both sweeps of a pair lie inside the slab,
+ * so every schedule is the same composition (bitwise the same results); the
+ * fused ones let the second sweep of a pair find the first one's output in
+ * the GPU's memory-side cache.  -1 (default) is 0, the fastest measured;
+ * slab_width 0 picks a slab of about 128 MB.  bfvm_get_schedule returns the
+ * schedule and width steps will use.  Errors: EINVAL. */
+int bfvm_set_schedule(bfvm_grid g, int32_t schedule, int64_t slab_width);
+int bfvm_get_schedule(bfvm_grid g, int32_t* schedule, int64_t* slab_width);
+
 /* Launch plan of a sweep axis, as chosen by the library or set by the
  * tuner.  kind: 0 one-thread-per-line two-pass kernel, 1 register-segmented
  * kernel with strided loads (y/z), 2 register-segmented kernel staged
- * through LDS (x).  m: elements per thread; w: waves per workgroup;
+ * through LDS (x), 3 the kind-1 kernel with every (row, substrate) of the x
+ * axis as one line (x).  m: elements per thread; w: waves per workgroup;
  * lpw: lines per wave (strided kernel) or rows per workgroup (LDS kernel).
  * bfvm_set_plan validates the plan against the grid and returns EINVAL
  * for one that does not fit (too few segments, LDS too large). */

@@ -30,7 +30,8 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ERANGE", -3: "ESTATE", -4: "EDEVICE", -5: 
 EXPORTS = [
     "bfvm_create", "bfvm_destroy", "bfvm_set_stream", "bfvm_set_params", "bfvm_set_sources",
     "bfvm_set_dirichlet", "bfvm_step", "bfvm_sweep", "bfvm_step_adjoint", "bfvm_read_field",
-    "bfvm_timing_enable", "bfvm_timing_read", "bfvm_timing_reset", "bfvm_get_plan", "bfvm_set_plan",
+    "bfvm_timing_enable", "bfvm_timing_read", "bfvm_timing_reset", "bfvm_timing_elements",
+    "bfvm_set_schedule", "bfvm_get_schedule", "bfvm_get_plan", "bfvm_set_plan",
     "bfvm_status_string", "bfvm_last_error", "bfvm_version",
 ]
 
@@ -74,6 +75,9 @@ def lib():
     L.bfvm_timing_enable.argtypes = [_vp, _i32]
     L.bfvm_timing_read.argtypes = [_vp, _i32, _f64p, _i64p]
     L.bfvm_timing_reset.argtypes = [_vp]
+    L.bfvm_timing_elements.argtypes = [_vp, _i32, _i64p]
+    L.bfvm_set_schedule.argtypes = [_vp, _i32, _i64]
+    L.bfvm_get_schedule.argtypes = [_vp, _i32p, _i64p]
     L.bfvm_get_plan.argtypes = [_vp, _i32, _i32p, _i32p, _i32p, _i32p]
     L.bfvm_set_plan.argtypes = [_vp, _i32, _i32, _i32, _i32, _i32]
     L.bfvm_status_string.argtypes = [ctypes.c_int]
@@ -230,6 +234,20 @@ class Grid:
 
     def set_plan(self, axis: int, kind: int, m: int = 0, w: int = 0, lpw: int = 0):
         _check(lib().bfvm_set_plan(self._handle, axis, kind, m, w, lpw), "bfvm_set_plan")
+
+    def set_schedule(self, schedule: int, slab_width: int = 0):
+        _check(lib().bfvm_set_schedule(self._handle, schedule, slab_width), "bfvm_set_schedule")
+
+    def get_schedule(self):
+        sc = ctypes.c_int32()
+        w = ctypes.c_int64()
+        _check(lib().bfvm_get_schedule(self._handle, ctypes.byref(sc), ctypes.byref(w)), "bfvm_get_schedule")
+        return sc.value, w.value
+
+    def timing_elements(self, stage: int) -> int:
+        n = ctypes.c_int64()
+        _check(lib().bfvm_timing_elements(self._handle, stage, ctypes.byref(n)), "bfvm_timing_elements")
+        return n.value
 
     def timing(self, enable: bool):
         _check(lib().bfvm_timing_enable(self._handle, 1 if enable else 0), "bfvm_timing_enable")

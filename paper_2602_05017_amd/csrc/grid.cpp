@@ -136,9 +136,10 @@ void time_begin(bfvm_grid g, int stage, hipEvent_t* a)
     (void)stage;
 }
 
-void time_end(bfvm_grid g, int stage, hipEvent_t a)
+void time_end(bfvm_grid g, int stage, hipEvent_t a, int64_t elems = 0)
 {
     if (!g->timing || !a) return;
+    g->stage_elems[stage] += elems;
     hipEvent_t b = g->ev_pool.back();
     g->ev_pool.pop_back();
     (void)hipEventRecord(b, g->stream);
@@ -182,17 +183,162 @@ int run_dirichlet(bfvm_grid g, void* u)
     return e == hipSuccess ? BFVM_OK : hip_fail(e, "dirichlet kernel");
 }
 
-int run_sweep(bfvm_grid g, int axis, const void* in, void* out, bool transposed)
+int run_sweep_geo(bfvm_grid g, int axis, const AxisGeom& geo, const void* in, void* out, bool transposed)
 {
-    const AxisGeom geo = axis_geom(axis, g->nx, g->ny, g->nz, g->S);
     const bool f32c = g->dtype == BFVM_F32_FAST;
     const void* invd = f32c ? (const void*)g->invd32[axis] : (const void*)g->invd64[axis];
     const void* r = f32c ? (const void*)g->r32[axis] : (const void*)g->r64[axis];
     hipEvent_t a;
     time_begin(g, 2 + axis, &a);
     hipError_t e = launch_sweep(g->dtype, transposed, g->plan[axis], geo, in, out, invd, r, g->stream);
-    time_end(g, 2 + axis, a);
+    time_end(g, 2 + axis, a, geo.n * geo.inner * geo.outer);
     return e == hipSuccess ? BFVM_OK : hip_fail(e, "sweep kernel");
+}
+
+int run_sweep(bfvm_grid g, int axis, const void* in, void* out, bool transposed)
+{
+    return run_sweep_geo(g, axis, axis_geom(axis, g->nx, g->ny, g->nz, g->S), in, out, transposed);
+}
+
+// ------------------------------------------------------- fused schedules
+// Slab size target for the fused schedules: a slab fits the 256 MB
+// memory-side cache, so the second sweep of a pair could read the first
+// sweep's output from it.  Measured on the 1000^3 x 4 grid, the smaller
+// launches cost more than the reuse saves, so the automatic choice is the
+// plain schedule; the fused ones stay selectable.
+const int64_t kSlabTarget = 128ll << 20;
+
+bool slab_plans_ok(bfvm_grid g)
+{
+    return g->plan[1].kind == PLAN_SEG_STRIDED && g->plan[2].kind == PLAN_SEG_STRIDED && g->nz <= 65535 &&
+           g->ny <= 65535;
+}
+
+// resolved schedule and slab width
+void resolve_schedule(bfvm_grid g, int* sched, int64_t* w)
+{
+    const int64_t col = g->ny * g->nz * (int64_t)g->S * (int64_t)dtype_size(g->dtype);
+    int sc = g->schedule;
+    if (sc < 0) sc = 0;
+    if (sc == 1 && !slab_plans_ok(g)) sc = 0;
+    if (sc == 2 && !(g->plan[0].kind == PLAN_SEG_XROWS && g->plan[1].kind == PLAN_SEG_STRIDED)) sc = 0;
+    if (sc == 2) {
+        const int64_t plane = g->nx * g->ny * (int64_t)g->S * (int64_t)dtype_size(g->dtype);
+        int64_t wz = g->slab_w > 0 ? g->slab_w : std::max<int64_t>(1, kSlabTarget / std::max<int64_t>(plane, 1));
+        *sched = sc;
+        *w = std::min<int64_t>(wz, g->nz);
+        return;
+    }
+    int64_t ww = g->slab_w;
+    if (ww <= 0) {
+        ww = std::max<int64_t>(1, kSlabTarget / std::max<int64_t>(col, 1));
+        // prefer slabs whose width * S fills whole 16-line tiles
+        for (int64_t c = ww; c >= 1; --c)
+            if ((c * g->S) % 16 == 0) { ww = c; break; }
+    }
+    *sched = sc;
+    *w = std::min<int64_t>(std::max<int64_t>(ww, 1), g->nx);
+}
+
+// Dirichlet entries regrouped by x-slab of width w (device copy)
+int build_dir_slabs(bfvm_grid g, int64_t w)
+{
+    if (g->dir_slab_w == w && !g->dir_slab_off.empty()) return BFVM_OK;
+    const int64_t nslab = (g->nx + w - 1) / w;
+    const int S = g->S;
+    int sc;
+    int64_t wr;
+    resolve_schedule(g, &sc, &wr);
+    const bool zs = sc == 2;
+    const int64_t nsl = zs ? (g->nz + w - 1) / w : nslab;
+    std::vector<std::vector<int64_t>> idx(nsl);
+    for (size_t i = 0; i < g->dir_elem_h.size(); ++i) {
+        const int64_t v = g->dir_elem_h[i] / S;
+        const int64_t c = zs ? v / (g->nx * g->ny) : v % g->nx;
+        idx[c / w].push_back((int64_t)i);
+    }
+    std::vector<int64_t> el, off(nsl + 1, 0);
+    std::vector<double> val;
+    for (int64_t k = 0; k < nsl; ++k) {
+        for (int64_t i : idx[k]) {
+            el.push_back(g->dir_elem_h[i]);
+            val.push_back(g->dir_val_h[i]);
+        }
+        off[k + 1] = (int64_t)el.size();
+    }
+    int st;
+    if ((st = dalloc_copy(g->dir_elem_slab, el.data(), el.size(), g->stream))) return st;
+    if ((st = dalloc_copy(g->dir_val_slab, val.data(), val.size(), g->stream))) return st;
+    g->dir_slab_off = off;
+    g->dir_slab_w = w;
+    return BFVM_OK;
+}
+
+// Rebuild the per-slab Dirichlet lists when the resolved schedule is the
+// fused one (called by the setters, so that a step never allocates).
+int refresh_dir_slabs(bfvm_grid g)
+{
+    int sc;
+    int64_t w;
+    resolve_schedule(g, &sc, &w);
+    if (sc != 1 && sc != 2) return BFVM_OK;
+    return build_dir_slabs(g, w);
+}
+
+int run_dirichlet_slab(bfvm_grid g, void* u, int64_t k)
+{
+    const int64_t a0 = g->dir_slab_off[k], a1 = g->dir_slab_off[k + 1];
+    if (a1 == a0) return BFVM_OK;
+    hipEvent_t a;
+    time_begin(g, 1, &a);
+    hipError_t e = launch_dirichlet(g->dtype, u, g->dir_elem_slab + a0, g->dir_val_slab + a0, a1 - a0, g->stream);
+    time_end(g, 1, a);
+    return e == hipSuccess ? BFVM_OK : hip_fail(e, "dirichlet kernel");
+}
+
+// One step with x and y back to back on z-slabs: Src, Dir, then per z-slab
+// X, Dir (slab entries), Y, then Dir, Z, Dir.  Rows and y lines stay inside
+// a z-slab, so this is again the plain composition.
+int run_step_zfused(bfvm_grid g, void* field, int64_t w)
+{
+    int st;
+    if ((st = run_source(g, field))) return st;
+    if ((st = run_dirichlet(g, field))) return st;
+    int64_t k = 0;
+    for (int64_t z0 = 0; z0 < g->nz; z0 += w, ++k) {
+        const int64_t z1 = std::min(g->nz, z0 + w);
+        if ((st = run_sweep_geo(g, 0, zslab_geom(0, g->nx, g->ny, g->nz, g->S, z0, z1), field, field, false)))
+            return st;
+        if ((st = run_dirichlet_slab(g, field, k))) return st;
+        if ((st = run_sweep_geo(g, 1, zslab_geom(1, g->nx, g->ny, g->nz, g->S, z0, z1), field, field, false)))
+            return st;
+    }
+    if ((st = run_dirichlet(g, field))) return st;
+    if ((st = run_sweep(g, 2, field, field, false))) return st;
+    return run_dirichlet(g, field);
+}
+
+// One step: Src, Dir, X, Dir, then per x-slab Y, Dir (slab entries), Z, then
+// Dir.  Every Dirichlet entry is still overwritten after its y sweep and
+// before its z sweep, and the y and z lines of a slab never leave it, so the
+// result is that of Src, Dir, X, Dir, Y, Dir, Z, Dir.
+int run_step_fused(bfvm_grid g, void* field, int64_t w)
+{
+    int st;
+    if ((st = run_source(g, field))) return st;
+    if ((st = run_dirichlet(g, field))) return st;
+    if ((st = run_sweep(g, 0, field, field, false))) return st;
+    if ((st = run_dirichlet(g, field))) return st;
+    int64_t k = 0;
+    for (int64_t x0 = 0; x0 < g->nx; x0 += w, ++k) {
+        const int64_t x1 = std::min(g->nx, x0 + w);
+        if ((st = run_sweep_geo(g, 1, slab_geom(1, g->nx, g->ny, g->nz, g->S, x0, x1), field, field, false)))
+            return st;
+        if ((st = run_dirichlet_slab(g, field, k))) return st;
+        if ((st = run_sweep_geo(g, 2, slab_geom(2, g->nx, g->ny, g->nz, g->S, x0, x1), field, field, false)))
+            return st;
+    }
+    return run_dirichlet(g, field);
 }
 
 int check_grid(bfvm_grid g)
@@ -253,6 +399,7 @@ int bfvm_create(bfvm_grid* out, int64_t nx, int64_t ny, int64_t nz, int32_t nsub
     if (hipGetDevice(&g->device) != hipSuccess) g->device = 0;
     for (int a = 0; a < 3; ++a)
         g->plan[a] = default_plan(a, axis_geom(a, nx, ny, nz, nsub), dtype);
+    (void)refresh_dir_slabs(g);   // no entries yet: empty lists, no allocation
     *out = g;
     return BFVM_OK;
 }
@@ -273,6 +420,8 @@ int bfvm_destroy(bfvm_grid g)
     dfree(g->src_invQ);
     dfree(g->dir_elem);
     dfree(g->dir_val);
+    dfree(g->dir_elem_slab);
+    dfree(g->dir_val_slab);
     dfree(g->red_partials);
     dfree(g->red_out);
     for (auto& p : g->pending) {
@@ -390,7 +539,11 @@ int bfvm_set_dirichlet(bfvm_grid g, int64_t count, const int64_t* voxel, const d
     if ((st = dalloc_copy(g->dir_elem, elem.data(), elem.size(), g->stream))) return st;
     if ((st = dalloc_copy(g->dir_val, val.data(), val.size(), g->stream))) return st;
     g->ndir = (int64_t)elem.size();
-    return BFVM_OK;
+    g->dir_elem_h = elem;
+    g->dir_val_h = val;
+    g->dir_slab_w = 0;
+    g->dir_slab_off.clear();
+    return refresh_dir_slabs(g);
 }
 
 int bfvm_step(bfvm_grid g, void* field, int64_t nsteps)
@@ -399,6 +552,16 @@ int bfvm_step(bfvm_grid g, void* field, int64_t nsteps)
     if (!field) return fail(BFVM_EINVAL, "field is NULL");
     if (nsteps < 0) return fail(BFVM_EINVAL, "nsteps must be >= 0");
     if (!g->have_params) return fail(BFVM_ESTATE, "set_params must come before step");
+    int sched;
+    int64_t w;
+    resolve_schedule(g, &sched, &w);
+    if (sched == 1 || sched == 2) {
+        if (g->dir_slab_w != w || g->dir_slab_off.empty())
+            return fail(BFVM_ESTATE, "per-slab Dirichlet lists are stale");
+        for (int64_t t = 0; t < nsteps; ++t)
+            if (int st = sched == 1 ? run_step_fused(g, field, w) : run_step_zfused(g, field, w)) return st;
+        return BFVM_OK;
+    }
     for (int64_t t = 0; t < nsteps; ++t) {
         int st;
         if ((st = run_source(g, field))) return st;
@@ -519,7 +682,41 @@ int bfvm_timing_reset(bfvm_grid g)
     for (int i = 0; i < 5; ++i) {
         g->stage_ms[i] = 0;
         g->stage_count[i] = 0;
+        g->stage_elems[i] = 0;
     }
+    return BFVM_OK;
+}
+
+int bfvm_timing_elements(bfvm_grid g, int32_t stage, int64_t* elements)
+{
+    if (int st = check_grid(g)) return st;
+    if (stage < 0 || stage > 4 || !elements) return fail(BFVM_EINVAL, "bad stage or NULL");
+    time_harvest(g);
+    *elements = g->stage_elems[stage];
+    return BFVM_OK;
+}
+
+int bfvm_set_schedule(bfvm_grid g, int32_t schedule, int64_t slab_width)
+{
+    if (int st = check_grid(g)) return st;
+    if (schedule < -1 || schedule > 2) return fail(BFVM_EINVAL, "schedule must be -1, 0, 1 or 2");
+    if (slab_width < 0) return fail(BFVM_EINVAL, "slab_width must be >= 0");
+    g->schedule = schedule;
+    g->slab_w = slab_width;
+    g->dir_slab_w = 0;
+    g->dir_slab_off.clear();
+    return refresh_dir_slabs(g);
+}
+
+int bfvm_get_schedule(bfvm_grid g, int32_t* schedule, int64_t* slab_width)
+{
+    if (int st = check_grid(g)) return st;
+    if (!schedule || !slab_width) return fail(BFVM_EINVAL, "NULL pointer");
+    int sc;
+    int64_t w;
+    resolve_schedule(g, &sc, &w);
+    *schedule = sc;
+    *slab_width = w;
     return BFVM_OK;
 }
 
@@ -548,7 +745,9 @@ int bfvm_set_plan(bfvm_grid g, int32_t axis, int32_t kind, int32_t m, int32_t w,
     const std::string why = check_plan(p, axis_geom(axis, g->nx, g->ny, g->nz, g->S), g->dtype);
     if (!why.empty()) return fail(BFVM_EINVAL, "plan does not fit: " + why);
     g->plan[axis] = p;
-    return BFVM_OK;
+    g->dir_slab_w = 0;
+    g->dir_slab_off.clear();
+    return refresh_dir_slabs(g);
 }
 
 }  // extern "C"

@@ -29,9 +29,17 @@ struct AxisGeom {
     int64_t stride;
     int64_t outer_stride;
     int32_t S;
+    int64_t p0 = 0;   // offset of line 0 inside the inner range (a multiple of S)
+    int64_t o0 = 0;   // offset of outer index 0
+    int32_t axis = 0; // 0 x, 1 y, 2 z (names the kernel instance in profiles)
 };
 
 AxisGeom axis_geom(int axis, int64_t nx, int64_t ny, int64_t nz, int32_t S);
+// The y (axis 1) or z (axis 2) lines of the x-slab [x0, x1): both stay inside
+// the slab, so the two sweeps can run back to back on one slab.
+AxisGeom slab_geom(int axis, int64_t nx, int64_t ny, int64_t nz, int32_t S, int64_t x0, int64_t x1);
+// The x (axis 0) or y (axis 1) lines of the z-slab [z0, z1).
+AxisGeom zslab_geom(int axis, int64_t nx, int64_t ny, int64_t nz, int32_t S, int64_t z0, int64_t z1);
 
 // Launch plan of one sweep (see bfvm_get_plan in bfvm.h).
 enum PlanKind { PLAN_LINE = 0, PLAN_SEG_STRIDED = 1, PLAN_SEG_XTILE = 2, PLAN_SEG_XROWS = 3 };
@@ -120,8 +128,22 @@ struct bfvm_grid_s {
     int64_t ndir = 0;
     int64_t* dir_elem = nullptr;
     double* dir_val = nullptr;
+    std::vector<int64_t> dir_elem_h;   // host copies (sorted by element)
+    std::vector<double> dir_val_h;
 
     bfvm::SweepPlan plan[3];
+
+    // step schedule: 0 = three full sweeps; 1 = x sweep, then y and z back to
+    // back on x-slabs of slab_w columns; 2 = x and y back to back on z-slabs
+    // of slab_w planes, then the z sweep (slab_w = 0: chosen automatically)
+    int32_t schedule = -1;   // -1 = automatic
+    int64_t slab_w = 0;
+    // Dirichlet entries sorted by x-slab (for the fused schedule): slab k owns
+    // dir entries [dir_slab_off[k], dir_slab_off[k+1])
+    int64_t dir_slab_w = 0;
+    std::vector<int64_t> dir_slab_off;
+    int64_t* dir_elem_slab = nullptr;
+    double* dir_val_slab = nullptr;
 
     // adjoint workspace
     void* work[3] = {nullptr, nullptr, nullptr};
@@ -136,6 +158,7 @@ struct bfvm_grid_s {
     std::vector<Pending> pending;
     double stage_ms[5] = {0, 0, 0, 0, 0};
     int64_t stage_count[5] = {0, 0, 0, 0, 0};
+    int64_t stage_elems[5] = {0, 0, 0, 0, 0};
 
     int64_t nvox() const { return nx * ny * nz; }
     int64_t nelem() const { return nx * ny * nz * (int64_t)S; }

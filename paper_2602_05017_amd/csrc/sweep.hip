@@ -38,6 +38,7 @@ AxisGeom axis_geom(int axis, int64_t nx, int64_t ny, int64_t nz, int32_t S)
 {
     AxisGeom g;
     g.S = S;
+    g.axis = axis;
     if (axis == 0) {
         g.n = nx; g.inner = S; g.outer = nz * ny; g.stride = S; g.outer_stride = nx * S;
     } else if (axis == 1) {
@@ -46,6 +47,32 @@ AxisGeom axis_geom(int axis, int64_t nx, int64_t ny, int64_t nz, int32_t S)
         g.n = nz; g.inner = ny * nx * S; g.outer = 1; g.stride = ny * nx * S;
         g.outer_stride = ny * nx * S * nz;
     }
+    return g;
+}
+
+AxisGeom slab_geom(int axis, int64_t nx, int64_t ny, int64_t nz, int32_t S, int64_t x0, int64_t x1)
+{
+    AxisGeom g;
+    g.S = S;
+    g.axis = axis;
+    g.inner = (x1 - x0) * S;
+    g.p0 = x0 * S;
+    if (axis == 1) {   // lines (z, x in slab, s) along y
+        g.n = ny; g.outer = nz; g.stride = nx * S; g.outer_stride = ny * nx * S;
+    } else {           // lines (y, x in slab, s) along z
+        g.n = nz; g.outer = ny; g.stride = ny * nx * S; g.outer_stride = nx * S;
+    }
+    return g;
+}
+
+AxisGeom zslab_geom(int axis, int64_t nx, int64_t ny, int64_t nz, int32_t S, int64_t z0, int64_t z1)
+{
+    AxisGeom g = axis_geom(axis, nx, ny, z1 - z0, S);
+    g.axis = axis;
+    if (axis == 0)      // rows (z, y) of the slab: lines start after z0*ny rows
+        g.p0 = z0 * ny * S;
+    else                // y lines of planes z0 .. z1-1
+        g.o0 = z0;
     return g;
 }
 
@@ -59,10 +86,10 @@ __global__ __launch_bounds__(256) void k_sweep_line(const T* in, T* out, AxisGeo
     const int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (L >= g.inner * g.outer) return;
     const int64_t o = L / g.inner;
-    const int64_t p = L - o * g.inner;
+    const int64_t p = g.p0 + (L - o * g.inner);
     const int S = g.S;
     const int s = (int)(p % S);
-    const int64_t base = o * g.outer_stride + p;
+    const int64_t base = (g.o0 + o) * g.outer_stride + p;
     const int64_t n = g.n, st = g.stride;
     const C r = rr[s];
     if (!TR) {
@@ -346,14 +373,15 @@ __global__ __launch_bounds__(1024) void k_sweep_seg_strided(const T* in, T* out,
     const bool valid = p < g.inner;
     const int64_t pa = valid ? p : g.inner - 1;          // clamped line for padding loads
     const int S = g.S;
-    const int s = (int)(pa % S);
+    const int s = (int)((g.p0 + pa) % S);
     const int64_t i0 = (int64_t)seg * M;
     const int64_t last = g.n - 1 - i0;                    // slots k > last are padding
     const int cnt = !valid || last < 0 ? 0 : (last >= M ? M : (int)last + 1);
     const int64_t st = g.stride;
     // XROWS: the x axis run through this kernel; line pa is substrate pa % S of
     // row pa / S, whose elements are S apart inside the row's n*S run
-    const int64_t line0 = XROWS ? (pa / S) * (g.n * S) + (pa % S) : (int64_t)blockIdx.y * g.outer_stride + pa;
+    const int64_t line0 = XROWS ? ((g.p0 + pa) / S) * (g.n * S) + (pa % S)
+                                : (g.o0 + (int64_t)blockIdx.y) * g.outer_stride + g.p0 + pa;
     const int64_t base = line0 + i0 * st;
     C v[M];
 #pragma unroll
@@ -680,7 +708,7 @@ static hipError_t launch_seg(const SweepPlan& p, const AxisGeom& g, const T* in,
         const size_t tab = (size_t)g.S * SP * sizeof(C);
         const int64_t KMS = (int64_t)K * M * g.S;
         const bool lds_tab = scan + tab <= (size_t)kMaxLDS && KMS < (1 << 24) && KMS * g.S <= (1ll << 40);
-        const bool zaxis = g.outer == 1;
+        const bool zaxis = g.axis == 2;
         if (xrows)
             hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, true, true, 0>), grid, dim3(threads), scan + tab,
                                st, in, out, gg, invd, r, p.lpw, SP, FastDiv((uint32_t)g.S));

@@ -35,9 +35,11 @@ def oracle_run(p, nsteps=None):
     return u
 
 
-def make_grid(p, dtype="f64", plans=None):
+def make_grid(p, dtype="f64", plans=None, schedule=None):
     import paper_2602_05017_amd as bf
     g = bf.Grid(p.nx, p.ny, p.nz, p.S, tuple(p.h), dtype=dtype)
+    if schedule is not None:
+        g.set_schedule(*schedule)
     g.set_params(p.D, p.lam, p.dt)
     if p.src is not None and len(p.src):
         g.set_sources(p.src.voxel, p.src.secretion, p.src.saturation, p.src.uptake)
@@ -54,9 +56,9 @@ def upload(p, g):
     return torch.from_numpy(np.ascontiguousarray(p.field())).to(device="cuda", dtype=g.torch_dtype)
 
 
-def gpu_run(p, dtype="f64", nsteps=None, plans=None):
+def gpu_run(p, dtype="f64", nsteps=None, plans=None, schedule=None):
     import torch
-    g = make_grid(p, dtype, plans)
+    g = make_grid(p, dtype, plans, schedule)
     u = upload(p, g)
     g.step(u, p.nsteps if nsteps is None else nsteps)
     torch.cuda.synchronize()

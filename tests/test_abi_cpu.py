@@ -165,3 +165,24 @@ def test_product_path_does_not_import_the_oracle():
             "bad = [m for m in sys.modules if m == 'oracle' or m.startswith('oracle.')]; "
             "assert not bad, bad")
     subprocess.run([sys.executable, "-c", code], check=True, cwd=ROOT)
+
+
+def test_schedule_selection_and_validation(L):
+    big = bf.Grid(1000, 1000, 1000, 4)
+    assert big.get_schedule()[0] == 0          # plain full sweeps by default
+    big.set_schedule(1)
+    assert big.get_schedule() == (1, 4)         # 128 MB x-slabs of a 32 GB field
+    big.set_schedule(0)
+    assert big.get_schedule()[0] == 0
+    big.set_schedule(1, 7)
+    assert big.get_schedule() == (1, 7)
+    big.set_schedule(2, 3)
+    assert big.get_schedule() == (2, 3)
+    with pytest.raises(bf.BfvmError):
+        big.set_schedule(3)
+    with pytest.raises(bf.BfvmError):
+        big.set_schedule(1, -1)
+    big.close()
+    small = bf.Grid(64, 64, 64, 1)
+    assert small.get_schedule()[0] == 0        # fits the memory-side cache: plain
+    small.close()

@@ -99,6 +99,27 @@ def test_xrows_kernel_plans(m, lpw):
     assert emax <= F64_TOL, (m, lpw, emax)
 
 
+@pytest.mark.parametrize("sched,w", [(1, 1), (1, 3), (1, 5), (1, 16), (1, 37), (2, 1), (2, 4), (2, 7), (2, 41)])
+@pytest.mark.parametrize("dtype,tol", [("f64", F64_TOL), ("f32", F32_TOL)])
+def test_fused_slab_schedule(sched, w, dtype, tol):
+    # two sweeps back to back on slabs, Dirichlet entries spread over the slabs
+    p = small_problem(NONCUBIC, 3, seed=380 + w, nsrc=300, ndir=60, nsteps=3)
+    ref = oracle_run(p)
+    got = gpu_run(p, dtype=dtype, schedule=(sched, w))
+    emax, _ = rel_err(got, ref)
+    assert emax <= tol, (w, emax)
+    assert np.all(got.reshape(-1, 3)[p.dr.voxel] == p.dr.value.astype(got.dtype))
+
+
+def test_fused_and_plain_schedules_agree_bitwise():
+    p = small_problem((40, 33, 27), 4, seed=390, nsrc=200, ndir=30, nsteps=3)
+    a = gpu_run(p, schedule=(0, 0))
+    b = gpu_run(p, schedule=(1, 6))
+    c = gpu_run(p, schedule=(2, 5))
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, c)
+
+
 def test_line_kernel_all_axes():
     p = small_problem(NONCUBIC, 2, seed=400, nsrc=100, ndir=10, nsteps=2)
     plans = {a: (0, 0, 0, 0) for a in range(3)}
