@@ -1,0 +1,69 @@
+"""Differentiable LOD time stepping on the GPU (torch.autograd.Function).
+
+Forward: N steps of the library's LOD step on a copy of the initial field,
+keeping every K-th state (checkpoints).  Backward: for each checkpoint
+segment in reverse, the segment's states are recomputed forward and the
+library's adjoint step (transposed Thomas solves in reverse axis order,
+transposed Dirichlet and source stages) is applied from the last step of the
+segment to the first, accumulating dL/du0 and the per-substrate dL/dD and
+dL/dlambda.  Device memory: ceil(N/K) checkpoints plus K recomputed states,
+plus the library's three-field adjoint workspace.
+
+The derivative of the step with respect to D and lambda follows from the
+zero-flux matrix A = (1 + beta) I + r L_N of App. A: dA/dr = L_N,
+dA/dbeta = I, with r = dt*D/h^2 and beta = dt*lambda/3 per axis.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import Grid
+
+
+class LODSteps(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, u0, D, lam, grid: Grid, dt: float, nsteps: int, checkpoint_every: int):
+        K = max(1, int(checkpoint_every))
+        grid.set_params(D.detach().cpu().double().numpy(), lam.detach().cpu().double().numpy(), dt)
+        u = u0.detach().to(grid.torch_dtype).contiguous().clone()
+        ckpts = []
+        for t in range(nsteps):
+            if t % K == 0:
+                ckpts.append(u.clone())
+            grid.step(u, 1)
+        ctx.grid = grid
+        ctx.nsteps = nsteps
+        ctx.K = K
+        ctx.in_dtype = u0.dtype
+        ctx.save_for_backward(*ckpts)
+        return u
+
+    @staticmethod
+    def backward(ctx, gout):
+        grid = ctx.grid
+        N, K = ctx.nsteps, ctx.K
+        ckpts = ctx.saved_tensors
+        g = gout.detach().to(grid.torch_dtype).contiguous().clone()
+        gD = np.zeros(grid.nsub)
+        gL = np.zeros(grid.nsub)
+        for c in range(len(ckpts) - 1, -1, -1):
+            seg0 = c * K
+            seg1 = min(seg0 + K, N)
+            states = [ckpts[c]]
+            for _ in range(seg0, seg1 - 1):
+                w = states[-1].clone()
+                grid.step(w, 1)
+                states.append(w)
+            for t in range(seg1 - 1, seg0 - 1, -1):
+                grid.step_adjoint(states[t - seg0], g, gD, gL)
+            del states
+        return (g.to(ctx.in_dtype), torch.from_numpy(gD), torch.from_numpy(gL), None, None, None, None)
+
+
+def simulate(grid: Grid, u0: torch.Tensor, D: torch.Tensor, lam: torch.Tensor, dt: float, nsteps: int,
+             checkpoint_every: int = 10) -> torch.Tensor:
+    """u_N after nsteps LOD steps from u0, differentiable in u0, D and lambda.
+
+    u0: CUDA tensor [nz, ny, nx, S]; D, lam: CPU float64 tensors [S]."""
+    return LODSteps.apply(u0, D, lam, grid, float(dt), int(nsteps), int(checkpoint_every))

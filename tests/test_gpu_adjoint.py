@@ -1,0 +1,169 @@
+"""GPU adjoint form: transposed sweeps in reverse axis order behind
+torch.autograd, checked against the oracle's adjoint, finite differences and
+closed-form eigenmode gradients; checkpointing must not change the result.
+
+Bars.  One LOD step's gradient (FP64) within 1e-12 of the oracle's.  Over N
+steps the gradient passes through 3N forward and 3N transposed sweeps whose
+rounding (reciprocal multiply on the GPU, division in the oracle) is
+amplified by at most the factors' conditioning, about 1 + 2r (21 at r = 10),
+per sweep: 6N * 21 * 2^-53 ~ 7e-13 at N = 50, so the multi-step bar is
+1e-11.  Central differences (h = 1e-6 relative, FP64 forward) within 1e-4.
+FP32 storage: dL/du0 and dL/dlambda within 1e-5 of the FP64 oracle; dL/dD
+sums y^T (L_N x), a difference of neighbouring stored values, which
+amplifies the 2^-24 storage rounding by the smoothness of the field, so it
+is held to the finite-difference bar 1e-4.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_helpers import make_grid, oracle_lists, rel_err, small_problem, upload
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_grad(p, target, nsteps, dtype="f64", K=10, D=None, lam=None):
+    import torch
+    import paper_2602_05017_amd as bf
+    from paper_2602_05017_amd.autograd import simulate
+    g = make_grid(p, dtype)
+    u0 = upload(p, g).requires_grad_(True)
+    Dt = torch.tensor(p.D if D is None else D, dtype=torch.float64, requires_grad=True)
+    Lt = torch.tensor(p.lam if lam is None else lam, dtype=torch.float64, requires_grad=True)
+    uN = simulate(g, u0, Dt, Lt, p.dt, nsteps, checkpoint_every=K)
+    tt = torch.from_numpy(target).to(device="cuda", dtype=uN.dtype)
+    loss = ((uN.double() - tt.double()) ** 2).sum()
+    loss.backward()
+    out = (float(loss), u0.grad.double().cpu().numpy(), Dt.grad.numpy().copy(), Lt.grad.numpy().copy())
+    g.close()
+    return out
+
+
+def _loss_gpu(p, target, nsteps, D, lam):
+    import torch
+    g = make_grid(p, "f64")
+    g.set_params(D, lam, p.dt)
+    u = upload(p, g)
+    g.step(u, nsteps)
+    torch.cuda.synchronize()
+    uN = g.read_field(u)
+    g.close()
+    return float(np.sum((uN - target) ** 2))
+
+
+def test_adjoint_step_matches_oracle():
+    import torch
+    p = small_problem((21, 17, 13), 3, seed=800, nsrc=80, ndir=12)
+    rng = np.random.default_rng(3)
+    gin = rng.random(p.shape) - 0.5
+    g = make_grid(p)
+    u = upload(p, g)
+    gg = torch.from_numpy(gin.copy()).cuda()
+    gD, gL = g.step_adjoint(u, gg)
+    torch.cuda.synchronize()
+    got = gg.cpu().numpy()
+    g.close()
+    src, dr = oracle_lists(p)
+    ref = gin.copy()
+    rD = np.zeros(p.S)
+    rL = np.zeros(p.S)
+    oracle.adjoint_step(np.array(p.u0), ref, rD, rL, p.h, p.D, p.lam, p.dt, src, dr)
+    assert rel_err(got, ref)[0] <= 1e-12
+    assert np.max(np.abs(gD - rD) / np.abs(rD)) <= 1e-12
+    assert np.max(np.abs(gL - rL) / np.abs(rL)) <= 1e-12
+
+
+@pytest.mark.parametrize("K", [1, 3, 10])
+def test_autograd_matches_oracle_gradient(K):
+    p = small_problem((24, 19, 22), 2, seed=810, nsrc=60, ndir=10, nsteps=7)
+    target = np.random.default_rng(4).random(p.shape)
+    L, g0, gD, gL = _gpu_grad(p, target, 7, K=K)
+    src, dr = oracle_lists(p)
+    rL_, ruN, rg0, rgD, rgL = oracle.run_with_gradient(p.u0, target, p.h, p.D, p.lam, p.dt, 7, src, dr)
+    assert abs(L - rL_) <= 1e-12 * rL_
+    assert rel_err(g0, rg0)[0] <= 1e-11
+    assert np.max(np.abs(gD - rgD) / np.abs(rgD)) <= 1e-11
+    assert np.max(np.abs(gL - rgL) / np.abs(rgL)) <= 1e-11
+
+
+def test_checkpointing_is_bitwise_neutral():
+    p = small_problem((20, 18, 16), 2, seed=820, nsrc=40, ndir=6, nsteps=9)
+    target = np.random.default_rng(5).random(p.shape)
+    a = _gpu_grad(p, target, 9, K=1)
+    b = _gpu_grad(p, target, 9, K=4)
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
+
+
+def test_central_differences_on_gpu():
+    p = small_problem((18, 15, 20), 2, seed=830, nsrc=50, ndir=8, nsteps=5)
+    target = np.random.default_rng(6).random(p.shape)
+    L, g0, gD, gL = _gpu_grad(p, target, 5)
+    for s in range(p.S):
+        for which, grad in (("D", gD), ("L", gL)):
+            base = p.D if which == "D" else p.lam
+            eps = 1e-6 * base[s]
+            plus, minus = base.copy(), base.copy()
+            plus[s] += eps
+            minus[s] -= eps
+            if which == "D":
+                fd = (_loss_gpu(p, target, 5, plus, p.lam) - _loss_gpu(p, target, 5, minus, p.lam)) / (2 * eps)
+            else:
+                fd = (_loss_gpu(p, target, 5, p.D, plus) - _loss_gpu(p, target, 5, p.D, minus)) / (2 * eps)
+            assert abs(grad[s] - fd) <= 1e-4 * abs(fd), (which, s, grad[s], fd)
+
+
+def test_eigenmode_closed_form_on_gpu():
+    nx, ny, nz = 20, 14, 24
+    ks = (3, 2, 5)
+    p = small_problem((nx, ny, nz), 1, seed=840, h=(10.0, 14.0, 9.0), dt=0.03, nsteps=5)
+    p.D = np.array([3e2])
+    p.lam = np.array([0.4])
+    cx = np.cos(np.pi * ks[0] * (np.arange(nx) + 0.5) / nx)
+    cy = np.cos(np.pi * ks[1] * (np.arange(ny) + 0.5) / ny)
+    cz = np.cos(np.pi * ks[2] * (np.arange(nz) + 0.5) / nz)
+    p.u0 = np.ascontiguousarray((cz[:, None, None] * cy[None, :, None] * cx[None, None, :])[..., None])
+    N = 5
+    L, g0, gD, gL = _gpu_grad(p, np.zeros(p.shape), N)
+    beta = p.dt * p.lam[0] / 3.0
+    mus, s2s = [], []
+    for n, k, a in ((nx, ks[0], 0), (ny, ks[1], 1), (nz, ks[2], 2)):
+        s2 = 4.0 * np.sin(np.pi * k / (2.0 * n)) ** 2
+        mus.append(1.0 + beta + p.dt * p.D[0] / p.h[a] ** 2 * s2)
+        s2s.append(s2)
+    Lref = np.sum(p.u0 ** 2) * np.prod([m ** (-2 * N) for m in mus])
+    gD_ref = sum(-2 * N * Lref * s2s[a] / mus[a] * p.dt / p.h[a] ** 2 for a in range(3))
+    gL_ref = -2 * N * Lref * sum(1.0 / m for m in mus) * p.dt / 3.0
+    assert abs(L - Lref) <= 1e-12 * Lref
+    assert abs(gD[0] - gD_ref) <= 1e-12 * abs(gD_ref)
+    assert abs(gL[0] - gL_ref) <= 1e-12 * abs(gL_ref)
+
+
+_C4_REF = {}
+
+
+def _c4_reference(p, target):
+    if "ref" not in _C4_REF:
+        src, dr = oracle_lists(p)
+        _C4_REF["ref"] = oracle.run_with_gradient(p.u0, target, p.h, p.D, p.lam, p.dt, p.nsteps, src, dr,
+                                                  checkpoint_every=10)
+    return _C4_REF["ref"]
+
+
+@pytest.mark.parametrize("dtype,tol,tolD", [("f64", 1e-11, 1e-11), ("f32", 1e-5, 1e-4)])
+def test_differentiation_workload_128cube(dtype, tol, tolD):
+    # 128^3 x 2, 50 steps, checkpoints every 10, loss = sum (u_N - target)^2;
+    # the variant with 1e3 source voxels and 16 Dirichlet voxels covers the
+    # transposed source and Dirichlet stages
+    p = workloads.config(4, n_sources=1000)
+    p.dr = workloads.dirichlet_variant(p, 16)
+    target = workloads.target_field(p)
+    L, g0, gD, gL = _gpu_grad(p, target, p.nsteps, dtype=dtype, K=10)
+    rL_, ruN, rg0, rgD, rgL = _c4_reference(p, target)
+    e0 = rel_err(g0, rg0)
+    eD = np.max(np.abs(gD - rgD) / np.abs(rgD))
+    eL = np.max(np.abs(gL - rgL) / np.abs(rgL))
+    print(f"128^3x2 {dtype} 50 steps: loss rel {abs(L - rL_) / rL_:.2e}, grad u0 e_max {e0[0]:.2e} "
+          f"e_2 {e0[1]:.2e}, grad D {eD:.2e}, grad lambda {eL:.2e}")
+    assert abs(L - rL_) <= tol * rL_
+    assert e0[0] <= tol and eL <= tol and eD <= tolD
