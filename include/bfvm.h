@@ -49,6 +49,7 @@ extern "C" {
 #define BFVM_ESTATE  (-3)   /* call out of order (e.g. step before set_params) */
 #define BFVM_EDEVICE (-4)   /* HIP runtime error; bfvm_last_error() has hipGetErrorString text */
 #define BFVM_ENOMEM  (-5)   /* host or device allocation failed */
+#define BFVM_EOFF    (-6)   /* the requested feature is switched off in this build */
 
 /* ---- storage / arithmetic types ---------------------------------------- */
 #define BFVM_F64       0    /* double storage, double arithmetic, double coefficients */
@@ -173,6 +174,82 @@ int bfvm_get_schedule(bfvm_grid g, int32_t* schedule, int64_t* slab_width);
  * for one that does not fit (too few segments, LDS too large). */
 int bfvm_get_plan(bfvm_grid g, int32_t axis, int32_t* kind, int32_t* m, int32_t* w, int32_t* lpw);
 int bfvm_set_plan(bfvm_grid g, int32_t axis, int32_t kind, int32_t m, int32_t w, int32_t lpw);
+
+/* ---- batched domains -------------------------------------------------- */
+/*
+ * Many independent grids (uneven sizes and substrate counts, any mix of
+ * storage types) advanced together.  Each domain's step is cut into work
+ * items per stage; in the default grouped mode one kernel launch per stage
+ * (a sweep stage: one launch per (storage type, elements per thread) class)
+ * covers that stage of every domain, and the launches of one step are
+ * captured once in a hipGraph and replayed.  Results are those of bfvm_step
+ * on each grid (the same Thomas constants, sources and Dirichlet lists; the
+ * x, y and z sweeps use the register-segmented solver with coefficients read
+ * from the global tables), up to the rounding of the reciprocal-based
+ * solver.  Not in the paper; the paper's closest knob is the block count of
+ * its pipelined x sweep (Sec. 3.2, Eq. 5).
+ *
+ * The member grids are borrowed: they must stay alive, and their params,
+ * sources and Dirichlet lists must not change, while the batch exists.
+ * Line lengths up to 256 are supported.  The batch's calls are not
+ * thread-safe; calls on one batch from several threads must be serialised.
+ */
+typedef struct bfvm_batch_s* bfvm_batch;
+
+#define BFVM_BATCH_GROUPED    0   /* one launch per stage over all domains (default) */
+#define BFVM_BATCH_PERSISTENT 1   /* one persistent launch per step: switched off (BFVM_EOFF) */
+
+/* grids[ndomains] (each with set_params done) and fields[ndomains] (device
+ * pointers, each holding its grid's field).  stream = hipStream_t; NULL makes
+ * the batch create its own non-blocking stream (graphs cannot capture the
+ * null stream).  Errors: EINVAL (sizes, NULLs, line longer than 256),
+ * ESTATE (a grid without params), ENOMEM, EDEVICE. */
+int bfvm_batch_create(bfvm_batch* out, int32_t ndomains, const bfvm_grid* grids, void* const* fields,
+                      void* stream);
+int bfvm_batch_destroy(bfvm_batch b);
+
+/* Select the execution mode.  BFVM_BATCH_PERSISTENT returns BFVM_EOFF: its
+ * cross-block dependency waits did not complete on gfx950.  Changing the
+ * mode resets the tile plans to the defaults.  Errors: EINVAL, EOFF. */
+int bfvm_batch_set_mode(bfvm_batch b, int32_t mode);
+
+/* Re-point the per-domain buffers (which = 0: fields, 1: gradients) without
+ * re-capturing: the kernels read the pointers from device descriptors at
+ * run time. */
+int bfvm_batch_set_fields(bfvm_batch b, int32_t which, void* const* ptrs);
+
+/* nsteps steps of every domain by replaying the captured graph (captured on
+ * the first call), then waits for the batch stream.  Errors: EINVAL,
+ * EDEVICE. */
+int bfvm_batch_step(bfvm_batch b, int64_t nsteps);
+/* The same with the launches enqueued directly (no graph). */
+int bfvm_batch_step_eager(bfvm_batch b, int64_t nsteps);
+
+/* One reverse step for the distinct domains subset[count] (fields = the
+ * state at the start of the step, gradients set with
+ * bfvm_batch_set_fields(b, 1, ...)): the adjoint of bfvm_step_adjoint for
+ * every domain of the subset, as one captured graph (rebuilt when the subset
+ * changes).  grad_D, grad_lambda: HOST arrays of sum_{i} nsub(subset[i])
+ * values, in subset order, INCREMENTED (per-item partial sums added on the
+ * host in a fixed order: deterministic).  Allocates the subset's workspace
+ * (three fields per domain) when the subset changes.
+ * Errors: EINVAL (incl. a repeated domain), ERANGE, ESTATE (no gradient
+ * buffers), ENOMEM, EDEVICE. */
+int bfvm_batch_step_adjoint(bfvm_batch b, int32_t count, const int32_t* subset, double* grad_D,
+                            double* grad_lambda);
+
+/* Autotuner: picks per (axis, line length, substrates, storage type) class
+ * the lines per tile (16, 32, 64) and elements per thread (4, 8, 16), and
+ * the work per item, by timing the batch step; reuses / writes a JSON cache
+ * at cache_path (NULL: no cache), keyed by the GPU architecture and mode.
+ * best_ms: the tuned step time.  Runs steps on the fields (their contents
+ * change). */
+int bfvm_batch_autotune(bfvm_batch b, const char* cache_path, double* best_ms);
+
+/* Elements per thread (m) and lines per tile (lpw) of a domain's axis. */
+int bfvm_batch_get_plan(bfvm_batch b, int32_t domain, int32_t axis, int32_t* m, int32_t* lpw);
+/* Work items of one forward step, kernel launches per step, work per item. */
+int bfvm_batch_info(bfvm_batch b, int64_t* items, int32_t* launches, int64_t* chunk_elems);
 
 /* Text of a status code, and the calling thread's last error detail. */
 const char* bfvm_status_string(int status);

@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libbfvm.so")
 
 F64, F32, F32_FAST = 0, 1, 2
 DTYPES = {"f64": F64, "f32": F32, "f32fast": F32_FAST}
-STATUS = {0: "OK", -1: "EINVAL", -2: "ERANGE", -3: "ESTATE", -4: "EDEVICE", -5: "ENOMEM"}
+STATUS = {0: "OK", -1: "EINVAL", -2: "ERANGE", -3: "ESTATE", -4: "EDEVICE", -5: "ENOMEM", -6: "EOFF"}
 
 # every entry point declared in include/bfvm.h
 EXPORTS = [
@@ -32,6 +32,9 @@ EXPORTS = [
     "bfvm_set_dirichlet", "bfvm_step", "bfvm_sweep", "bfvm_step_adjoint", "bfvm_read_field",
     "bfvm_timing_enable", "bfvm_timing_read", "bfvm_timing_reset", "bfvm_timing_elements",
     "bfvm_set_schedule", "bfvm_get_schedule", "bfvm_get_plan", "bfvm_set_plan",
+    "bfvm_batch_create", "bfvm_batch_destroy", "bfvm_batch_set_mode", "bfvm_batch_set_fields", "bfvm_batch_step",
+    "bfvm_batch_step_eager", "bfvm_batch_step_adjoint", "bfvm_batch_autotune", "bfvm_batch_get_plan",
+    "bfvm_batch_info",
     "bfvm_status_string", "bfvm_last_error", "bfvm_version",
 ]
 
@@ -80,6 +83,15 @@ def lib():
     L.bfvm_get_schedule.argtypes = [_vp, _i32p, _i64p]
     L.bfvm_get_plan.argtypes = [_vp, _i32, _i32p, _i32p, _i32p, _i32p]
     L.bfvm_set_plan.argtypes = [_vp, _i32, _i32, _i32, _i32, _i32]
+    L.bfvm_batch_create.argtypes = [ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]
+    L.bfvm_batch_destroy.argtypes = [_vp]
+    L.bfvm_batch_set_fields.argtypes = [_vp, _i32, ctypes.POINTER(_vp)]
+    L.bfvm_batch_step.argtypes = [_vp, _i64]
+    L.bfvm_batch_step_eager.argtypes = [_vp, _i64]
+    L.bfvm_batch_step_adjoint.argtypes = [_vp, _i32, _i32p, _f64p, _f64p]
+    L.bfvm_batch_autotune.argtypes = [_vp, ctypes.c_char_p, _f64p]
+    L.bfvm_batch_get_plan.argtypes = [_vp, _i32, _i32, _i32p, _i32p]
+    L.bfvm_batch_info.argtypes = [_vp, _i64p, _i32p, _i64p]
     L.bfvm_status_string.argtypes = [ctypes.c_int]
     L.bfvm_status_string.restype = ctypes.c_char_p
     L.bfvm_last_error.argtypes = []
@@ -281,3 +293,93 @@ class Grid:
 
 
 STAGES = {"source": 0, "dirichlet": 1, "x": 2, "y": 3, "z": 4}
+
+
+BATCH_MODES = {"grouped": 0, "persistent": 1}
+
+
+class Batch:
+    """Many grids stepped together, one graph replay per step.
+
+    grids: configured Grid objects (params, sources, Dirichlet set); fields: their
+    CUDA field tensors.  The grids and fields must outlive the batch.  mode:
+    "grouped" (one launch per stage over all domains); "persistent" is switched
+    off in the library and raises BfvmError (EOFF)."""
+
+    def __init__(self, grids, fields, stream=None, mode="grouped"):
+        n = len(grids)
+        if n != len(fields) or n == 0:
+            raise ValueError("need one field per grid")
+        self.grids = list(grids)
+        self.fields = list(fields)
+        hs = (_vp * n)(*[g.handle for g in grids])
+        fs = (_vp * n)(*[g._field_ptr(f) for g, f in zip(grids, fields)])
+        self._handle = _vp()
+        import torch
+        torch.cuda.synchronize()     # the batch runs on its own stream
+        _check(lib().bfvm_batch_create(ctypes.byref(self._handle), n, hs, fs, stream), "bfvm_batch_create")
+        if mode != "grouped":
+            try:
+                _check(lib().bfvm_batch_set_mode(self._handle, BATCH_MODES[mode]), "bfvm_batch_set_mode")
+            except Exception:
+                self.close()
+                raise
+
+    def _ptrs(self, tensors):
+        n = len(self.grids)
+        return (_vp * n)(*[g._field_ptr(t) if t is not None else None for g, t in zip(self.grids, tensors)])
+
+    def set_fields(self, fields):
+        self.fields = list(fields)
+        _check(lib().bfvm_batch_set_fields(self._handle, 0, self._ptrs(fields)), "bfvm_batch_set_fields")
+
+    def set_grads(self, grads):
+        _check(lib().bfvm_batch_set_fields(self._handle, 1, self._ptrs(grads)), "bfvm_batch_set_fields")
+
+    def step(self, nsteps: int = 1, graph: bool = True):
+        import torch
+        torch.cuda.synchronize()
+        fn = lib().bfvm_batch_step if graph else lib().bfvm_batch_step_eager
+        _check(fn(self._handle, int(nsteps)), "bfvm_batch_step")
+
+    def step_adjoint(self, subset, grad_D=None, grad_lambda=None):
+        import torch
+        torch.cuda.synchronize()
+        subset = np.ascontiguousarray(subset, dtype=np.int32)
+        tot = sum(self.grids[i].nsub for i in subset)
+        gD = np.zeros(tot) if grad_D is None else grad_D
+        gL = np.zeros(tot) if grad_lambda is None else grad_lambda
+        _check(lib().bfvm_batch_step_adjoint(self._handle, subset.size, subset.ctypes.data_as(_i32p),
+                                             _ptr(gD), _ptr(gL)), "bfvm_batch_step_adjoint")
+        return gD, gL
+
+    def autotune(self, cache_path=None) -> float:
+        import torch
+        torch.cuda.synchronize()
+        ms = ctypes.c_double()
+        path = cache_path.encode() if cache_path else None
+        _check(lib().bfvm_batch_autotune(self._handle, path, ctypes.byref(ms)), "bfvm_batch_autotune")
+        return ms.value
+
+    def plan(self, domain: int, axis: int):
+        m, l = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().bfvm_batch_get_plan(self._handle, domain, axis, ctypes.byref(m), ctypes.byref(l)),
+               "bfvm_batch_get_plan")
+        return m.value, l.value
+
+    def info(self):
+        it, bl, ch = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().bfvm_batch_info(self._handle, ctypes.byref(it), ctypes.byref(bl), ctypes.byref(ch)),
+               "bfvm_batch_info")
+        return {"items": it.value, "launches": bl.value, "chunk_elems": ch.value}
+
+    def close(self):
+        if self._handle:
+            lib().bfvm_batch_destroy(self._handle)
+            self._handle = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,1177 @@
+// Batched multi-domain stepping: many independent grids of uneven size,
+// substrate count and storage type advanced together, one captured hipGraph
+// replay per step.
+//
+// Each domain's step is a linear chain of stages (source, Dirichlet, x sweep,
+// Dirichlet, y sweep, Dirichlet, z sweep, Dirichlet; the adjoint step adds
+// copies, transposed sweeps, masks, reductions).  Every stage is cut into
+// work items (tiles of lines for sweeps, ranges for the sparse stages).
+//
+// Grouped mode (the default): one kernel launch per stage covers that stage
+// of EVERY domain, one block per item, so the order of the launches is the
+// order of the stages and no block ever waits for another.  A sweep stage is
+// split into one launch per (storage type, elements-per-thread) class, so
+// each launch runs a kernel compiled for exactly that register shape; the
+// lines per tile may differ between domains of a class.  A step is at most
+// 4 + 3 x (number of classes) launches, captured once and replayed.
+//
+// Persistent mode (switched off): ONE launch per step whose blocks take the
+// items of all stages from an atomic queue and wait, through per-(domain,
+// stage) completion counters, for the previous stage of their own domain.
+// On gfx950 its dependency waits did not complete, both with the counters in
+// ordinary device memory and in uncached memory; until the cause is known,
+// bfvm_batch_set_mode refuses it.  The scheduler is kept below unchanged.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "seg_solver.hpp"
+
+namespace bfvm {
+
+enum StageType : int32_t {
+    ST_SRC = 0,      // u <- (u + P) * invQ at source entries
+    ST_DIR = 1,      // u <- value at Dirichlet entries
+    ST_SWEEP = 2,    // Thomas sweep along axis
+    ST_SWEEP_T = 3,  // transposed sweep along axis
+    ST_MASK = 4,     // g <- 0 at Dirichlet entries
+    ST_SRC_T = 5,    // g <- g * invQ at source entries
+    ST_COPY = 6,     // buffer out <- buffer in
+    ST_REDUCE = 7,   // per-substrate sums of y (L_N x) and y x along axis
+};
+
+constexpr int kBatchThreads = 512;
+// elements per thread M in {4, 8} and at most 512/16 = 32 segments per line
+constexpr int64_t kMaxBatchLine = 256;
+constexpr int kNumBuf = 5;   // 0 field, 1 gradient, 2..4 adjoint workspace
+
+struct BDomain {
+    int32_t dtype;
+    int32_t S;
+    int64_t nx, ny, nz;
+    void* buf[kNumBuf];
+    const void* invd[3];
+    const void* r[3];
+    const int64_t* src_vox;
+    const double* src_P;
+    const double* src_invQ;
+    int64_t nsrc;
+    const int64_t* dir_elem;
+    const double* dir_val;
+    int64_t ndir;
+    int32_t M[3];
+    int32_t lpw[3];
+};
+
+struct BItem {
+    int32_t dom;
+    int32_t type;
+    int32_t axis;
+    int32_t in, out;
+    int32_t done;      // counter incremented when the item completes
+    int32_t dep;       // counter to wait for (-1: none)
+    uint32_t need;     // value of counter dep that means "stage complete"
+    int64_t a0, a1;    // range (tiles, entries, elements or voxels)
+    int64_t slot;      // REDUCE: offset of the item's 2*S partial sums
+};
+
+// ------------------------------------------------------------ device work
+
+struct SweepShape {
+    int64_t n, inner, outer, stride, outer_stride;
+    bool xrows;
+    int64_t row_len;
+};
+
+__device__ __forceinline__ SweepShape sweep_shape(const BDomain& d, int axis)
+{
+    SweepShape q;
+    const int64_t S = d.S;
+    q.xrows = axis == 0;
+    q.row_len = d.nx * S;
+    if (axis == 0) {
+        q.n = d.nx; q.inner = d.ny * d.nz * S; q.outer = 1; q.stride = S; q.outer_stride = 0;
+    } else if (axis == 1) {
+        q.n = d.ny; q.inner = d.nx * S; q.outer = d.nz; q.stride = d.nx * S; q.outer_stride = d.ny * d.nx * S;
+    } else {
+        q.n = d.nz; q.inner = d.nx * d.ny * S; q.outer = 1; q.stride = d.nx * d.ny * S; q.outer_stride = 0;
+    }
+    return q;
+}
+
+// One tile of lpw lines (all K = blockDim/lpw segments), as in the strided
+// sweep kernel, with coefficients read from the global table.
+template <typename T, typename C, int M, bool TR>
+__device__ void batch_tile(const T* in, T* out, const SweepShape& q, int S, int lpw, int64_t ox, int64_t oy,
+                           const C* __restrict__ invd, const C* __restrict__ rr, C* sc)
+{
+    const int K = blockDim.x / lpw;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int line = lane % lpw;
+    const int seg = wave * (64 / lpw) + lane / lpw;
+    const int64_t p = ox * lpw + line;
+    const bool valid = p < q.inner;
+    const int64_t pa = valid ? p : q.inner - 1;
+    const int s = (int)(pa % S);
+    const int64_t i0 = (int64_t)seg * M;
+    const int64_t last = q.n - 1 - i0;
+    const int cnt = !valid || last < 0 ? 0 : (last >= M ? M : (int)last + 1);
+    const int64_t st = q.stride;
+    const int64_t line0 = q.xrows ? (pa / S) * q.row_len + (pa % S) : oy * q.outer_stride + pa;
+    const int64_t base = line0 + i0 * st;
+    C v[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) v[k] = (C)in[base + (k <= last ? k : last) * st];
+    const C r = rr[s];
+    RegCoef<C, M> coef;
+    coef.prev = (TR && i0 > 0 && last >= 0) ? invd[(i0 - 1) * S + s] : (C)0;
+    const C* cf = invd + (last >= 0 ? i0 * S + s : s);
+#pragma unroll
+    for (int k = 0; k < M; ++k) coef.b[k] = k <= last ? cf[(k <= last ? k : 0) * S] : (C)0;
+    solve_segment<C, M, TR>(v, seg, K, line, lpw, r, coef, sc, true);
+    T* op = out + base;
+    asm volatile("" : "+v"(op));
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+        if (k < cnt) op[k * st] = (T)v[k];
+}
+
+template <typename T, typename C, bool TR>
+__device__ void batch_sweep_item(const BDomain& d, const BItem& it, C* sc)
+{
+    const SweepShape q = sweep_shape(d, it.axis);
+    const int lpw = d.lpw[it.axis];
+    const int64_t tpo = (q.inner + lpw - 1) / lpw;   // tiles per outer index
+    const T* in = static_cast<const T*>(d.buf[it.in]);
+    T* out = static_cast<T*>(d.buf[it.out]);
+    const C* invd = static_cast<const C*>(d.invd[it.axis]);
+    const C* rr = static_cast<const C*>(d.r[it.axis]);
+    for (int64_t t = it.a0; t < it.a1; ++t) {
+        const int64_t oy = t / tpo, ox = t - oy * tpo;
+        if (d.M[it.axis] == 4)
+            batch_tile<T, C, 4, TR>(in, out, q, d.S, lpw, ox, oy, invd, rr, sc);
+        else
+            batch_tile<T, C, 8, TR>(in, out, q, d.S, lpw, ox, oy, invd, rr, sc);
+    }
+}
+
+template <typename T>
+__device__ void batch_sparse_item(const BDomain& d, const BItem& it, double* partials, double* red)
+{
+    const int S = d.S;
+    switch (it.type) {
+        case ST_SRC: {
+            T* u = static_cast<T*>(d.buf[it.out]);
+            for (int64_t t = it.a0 + threadIdx.x; t < it.a1; t += blockDim.x) {
+                const int64_t k = t / S;
+                const int64_t e = d.src_vox[k] * S + (t - k * S);
+                u[e] = (T)(((double)u[e] + d.src_P[t]) * d.src_invQ[t]);
+            }
+            break;
+        }
+        case ST_SRC_T: {
+            T* g = static_cast<T*>(d.buf[it.out]);
+            for (int64_t t = it.a0 + threadIdx.x; t < it.a1; t += blockDim.x) {
+                const int64_t k = t / S;
+                const int64_t e = d.src_vox[k] * S + (t - k * S);
+                g[e] = (T)((double)g[e] * d.src_invQ[t]);
+            }
+            break;
+        }
+        case ST_DIR: {
+            T* u = static_cast<T*>(d.buf[it.out]);
+            for (int64_t t = it.a0 + threadIdx.x; t < it.a1; t += blockDim.x) u[d.dir_elem[t]] = (T)d.dir_val[t];
+            break;
+        }
+        case ST_MASK: {
+            T* g = static_cast<T*>(d.buf[it.out]);
+            for (int64_t t = it.a0 + threadIdx.x; t < it.a1; t += blockDim.x) g[d.dir_elem[t]] = (T)0;
+            break;
+        }
+        case ST_COPY: {
+            const T* a = static_cast<const T*>(d.buf[it.in]);
+            T* b = static_cast<T*>(d.buf[it.out]);
+            for (int64_t t = it.a0 + threadIdx.x; t < it.a1; t += blockDim.x) b[t] = a[t];
+            break;
+        }
+        case ST_REDUCE: {
+            // y = buffer in (gradient after the transposed sweep), x = buffer
+            // out (the forward sweep's output); sums over voxels [a0, a1)
+            const T* y = static_cast<const T*>(d.buf[it.in]);
+            const T* x = static_cast<const T*>(d.buf[it.out]);
+            const SweepShape q = sweep_shape(d, it.axis);
+            const int64_t vstride = it.axis == 0 ? 1 : (it.axis == 1 ? d.nx : d.nx * d.ny);
+            const int64_t est = vstride * S;
+            for (int s = 0; s < S; ++s) {
+                double a0 = 0.0, a1 = 0.0;
+                for (int64_t v = it.a0 + threadIdx.x; v < it.a1; v += blockDim.x) {
+                    const int64_t i = (v / vstride) % q.n;
+                    const int64_t e = v * S + s;
+                    const double xe = (double)x[e];
+                    double lx = 0.0;
+                    if (i > 0) lx += xe - (double)x[e - est];
+                    if (i < q.n - 1) lx += xe - (double)x[e + est];
+                    const double ye = (double)y[e];
+                    a0 += ye * lx;
+                    a1 += ye * xe;
+                }
+                red[threadIdx.x] = a0;
+                red[blockDim.x + threadIdx.x] = a1;
+                __syncthreads();
+                for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+                    if ((int)threadIdx.x < w) {
+                        red[threadIdx.x] += red[threadIdx.x + w];
+                        red[blockDim.x + threadIdx.x] += red[blockDim.x + threadIdx.x + w];
+                    }
+                    __syncthreads();
+                }
+                if (threadIdx.x == 0) {
+                    partials[it.slot + 2 * s + 0] = red[0];
+                    partials[it.slot + 2 * s + 1] = red[blockDim.x];
+                }
+                __syncthreads();
+            }
+            break;
+        }
+        default: break;
+    }
+}
+
+
+// ------------------------------------------------------------ grouped mode
+
+// One block per item of one sweep stage (one storage type and M).
+template <typename T, typename C, int M, bool TR>
+__global__ __launch_bounds__(kBatchThreads) void k_group_sweep(const BDomain* __restrict__ doms,
+                                                               const BItem* __restrict__ items)
+{
+    __shared__ __align__(16) C sc[4 * kBatchThreads];   // carry arrays
+    const BItem it = items[blockIdx.x];
+    const BDomain& d = doms[it.dom];
+    const SweepShape q = sweep_shape(d, it.axis);
+    const int lpw = d.lpw[it.axis];
+    const int64_t tpo = (q.inner + lpw - 1) / lpw;   // tiles per outer index
+    const T* in = static_cast<const T*>(d.buf[it.in]);
+    T* out = static_cast<T*>(d.buf[it.out]);
+    const C* invd = static_cast<const C*>(d.invd[it.axis]);
+    const C* rr = static_cast<const C*>(d.r[it.axis]);
+    for (int64_t t = it.a0; t < it.a1; ++t) {
+        const int64_t oy = t / tpo, ox = t - oy * tpo;
+        batch_tile<T, C, M, TR>(in, out, q, d.S, lpw, ox, oy, invd, rr, sc);
+    }
+}
+
+// One block per item of one sparse stage (source, Dirichlet, mask, copy,
+// reduction) of one storage type.
+__global__ __launch_bounds__(kBatchThreads) void k_group_sparse(const BDomain* __restrict__ doms,
+                                                                const BItem* __restrict__ items, double* partials)
+{
+    __shared__ double red[2 * kBatchThreads];
+    const BItem it = items[blockIdx.x];
+    const BDomain& d = doms[it.dom];
+    if (d.dtype == DT_F64) batch_sparse_item<double>(d, it, partials, red);
+    else batch_sparse_item<float>(d, it, partials, red);
+}
+
+// ------------------------------------------------- persistent mode (off)
+
+__global__ void k_batch_reset(uint32_t* counters, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        counters[i] = 0;
+}
+
+// counters[0] = queue head, counters[1] = error flag, counters[2 + c] = stage
+// counters; all in uncached device memory (see CounterPool).
+// At least 4 waves per SIMD (two 512-thread blocks per CU): every variant
+// must fit 128 VGPRs.
+__global__ __launch_bounds__(kBatchThreads, 4) void k_batch(const BDomain* __restrict__ doms,
+                                                         const BItem* __restrict__ items, int64_t nitems,
+                                                         uint32_t* counters, double* partials,
+                                                         uint64_t limit_ticks)
+{
+    __shared__ __align__(16) double sc[4 * kBatchThreads];   // carry arrays (also the reduction buffer)
+    __shared__ int64_t s_item;
+    uint32_t* head = counters;
+    uint32_t* err = counters + 1;
+    uint32_t* cnt = counters + 2;
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_item = (int64_t)__hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int64_t idx = s_item;
+        __syncthreads();
+        if (idx >= nitems) break;
+        const BItem it = items[idx];
+        if (threadIdx.x == 0 && it.dep >= 0) {
+            // Wait (bounded in wall-clock time) for the previous stage of this
+            // domain.  The counters live in uncached memory, so plain polls
+            // read memory; one acquire fence follows a successful wait.  Once
+            // any wait has failed, no block waits again.
+            const uint64_t t0 = wall_clock64();
+            bool ok = true;
+            while (__hip_atomic_load(&cnt[it.dep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < it.need) {
+                if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = false; break; }
+                __builtin_amdgcn_s_sleep(2);
+                if (wall_clock64() - t0 > limit_ticks) {
+                    __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = false;
+                    break;
+                }
+            }
+            if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+        const BDomain& d = doms[it.dom];
+        if (it.type == ST_SWEEP || it.type == ST_SWEEP_T) {
+            const bool tr = it.type == ST_SWEEP_T;
+            if (d.dtype == DT_F64) {
+                if (tr) batch_sweep_item<double, double, true>(d, it, sc);
+                else batch_sweep_item<double, double, false>(d, it, sc);
+            } else if (d.dtype == DT_F32) {
+                if (tr) batch_sweep_item<float, double, true>(d, it, sc);
+                else batch_sweep_item<float, double, false>(d, it, sc);
+            } else {
+                float* scf = reinterpret_cast<float*>(sc);
+                if (tr) batch_sweep_item<float, float, true>(d, it, scf);
+                else batch_sweep_item<float, float, false>(d, it, scf);
+            }
+        } else {
+            if (d.dtype == DT_F64) batch_sparse_item<double>(d, it, partials, sc);
+            else batch_sparse_item<float>(d, it, partials, sc);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            // publish the item's writes (L2 write-back), then count it
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_fetch_add(&cnt[it.done], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+
+}  // namespace bfvm
+
+// ===================================================================== host
+
+using namespace bfvm;
+
+namespace {
+
+int bfail(int code, const std::string& msg)
+{
+    set_error(msg);
+    return code;
+}
+
+#define BHIP(expr, what)                                                                   \
+    do {                                                                                   \
+        hipError_t _e = (expr);                                                            \
+        if (_e != hipSuccess) return bfail(BFVM_EDEVICE, std::string(what) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+// The single-launch persistent mode is switched off: on gfx950 its
+// dependency waits did not complete (see the file header).  Its scheduler is
+// kept so that it can be re-enabled once the cause is known.
+constexpr bool kPersistentModeEnabled = false;
+
+struct Stage {
+    int32_t type, axis, in, out;
+};
+
+// One kernel launch of the grouped mode: the items [off, off + count) of one
+// stage (sweeps: one (storage type, M) class of that stage), one block each.
+struct Launch {
+    int32_t sweep;     // 1: k_group_sweep, 0: k_group_sparse
+    int32_t dtype, M;
+    bool tr;
+    int64_t off, count;
+};
+
+struct Program {
+    std::vector<BItem> items;        // stage-major (host copy)
+    std::vector<Launch> launches;    // grouped mode, in program order
+    int64_t ncounters = 0;           // persistent mode
+    int64_t npartials = 0;
+    BItem* d_items = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+void drop_graph(Program& P)
+{
+    if (P.exec) (void)hipGraphExecDestroy(P.exec);
+    if (P.graph) (void)hipGraphDestroy(P.graph);
+    P.exec = nullptr;
+    P.graph = nullptr;
+}
+
+void free_program(Program& P)
+{
+    drop_graph(P);
+    if (P.d_items) (void)hipFree(P.d_items);
+    P.d_items = nullptr;
+    P.items.clear();
+    P.launches.clear();
+}
+
+}  // namespace
+
+struct bfvm_batch_s {
+    std::vector<bfvm_grid> grids;
+    std::vector<BDomain> doms;        // host copy of the descriptors
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int mode = BFVM_BATCH_GROUPED;
+    BDomain* d_doms = nullptr;
+    int64_t chunk_elems = 1 << 14;    // work per item
+    int blocks = 0;                   // persistent grid size
+    uint64_t wait_ticks = 0;          // bound of one dependency wait (wall-clock ticks)
+    Program fwd;                      // one step of every domain
+    Program adj;                      // one reverse step of adj_subset
+    std::vector<int32_t> adj_subset;
+    double* d_partials = nullptr;
+    int64_t partials_cap = 0;
+    uint32_t* d_counters = nullptr;   // persistent mode only
+    int64_t counters_cap = 0;
+    void* work_mem = nullptr;         // adjoint workspace of the subset
+};
+
+namespace {
+
+int64_t tiles_of(const BDomain& d, int axis)
+{
+    int64_t inner, outer;
+    if (axis == 0) { inner = d.ny * d.nz * d.S; outer = 1; }
+    else if (axis == 1) { inner = d.nx * d.S; outer = d.nz; }
+    else { inner = d.nx * d.ny * d.S; outer = 1; }
+    return (inner + d.lpw[axis] - 1) / d.lpw[axis] * outer;
+}
+
+int64_t axis_len(const BDomain& d, int axis) { return axis == 0 ? d.nx : (axis == 1 ? d.ny : d.nz); }
+
+bool plan_fits(int64_t n, int M, int lpw) { return (int64_t)(kBatchThreads / lpw) * M >= n; }
+
+const int kBatchM[] = {4, 8, 16};
+
+// smallest supported elements-per-thread whose K = 512 / lpw segments cover n
+int smallest_m(int64_t n, int lpw, int max_m)
+{
+    for (int m : kBatchM)
+        if (m <= max_m && plan_fits(n, m, lpw)) return m;
+    return 0;
+}
+
+int max_m_for_mode(int mode) { return mode == BFVM_BATCH_PERSISTENT ? 8 : 16; }
+
+// default per-axis plan: the most lines per tile (widest coalesced rows)
+// whose segments of at most 8 elements still cover the line (16 only if
+// the autotuner finds it faster: it doubles the registers per thread)
+void default_batch_plan(BDomain& d, int mode)
+{
+    (void)mode;
+    for (int a = 0; a < 3; ++a) {
+        const int64_t n = axis_len(d, a);
+        for (int l : {64, 32, 16}) {
+            const int m = smallest_m(n, l, 8);
+            if (m) {
+                d.M[a] = m;
+                d.lpw[a] = l;
+                break;
+            }
+        }
+    }
+}
+
+// Build a program (per-domain stage chains) over domains `which`: items in
+// stage-major order, the grouped launches, and the persistent mode's counters.
+void build_program(bfvm_batch b, const std::vector<int32_t>& which, const std::vector<Stage>& prog, Program& P)
+{
+    P.items.clear();
+    P.launches.clear();
+    const int ns = (int)prog.size();
+    std::vector<std::vector<std::vector<BItem>>> per(which.size(), std::vector<std::vector<BItem>>(ns));
+    int64_t partials = 0;
+    for (int k = 0; k < ns; ++k) {
+        const Stage& sg = prog[k];
+        for (size_t wi = 0; wi < which.size(); ++wi) {
+            const BDomain& d = b->doms[which[wi]];
+            const int64_t nel = d.nx * d.ny * d.nz * d.S;
+            int64_t total = 0, chunk = 1;
+            switch (sg.type) {
+                case ST_SRC: case ST_SRC_T: total = d.nsrc * d.S; chunk = b->chunk_elems; break;
+                case ST_DIR: case ST_MASK: total = d.ndir; chunk = b->chunk_elems; break;
+                case ST_COPY: total = nel; chunk = b->chunk_elems; break;
+                case ST_REDUCE: total = d.nx * d.ny * d.nz; chunk = std::max<int64_t>(1, b->chunk_elems / d.S); break;
+                default: {
+                    total = tiles_of(d, sg.axis);
+                    const int64_t per_tile = (int64_t)d.lpw[sg.axis] * axis_len(d, sg.axis);
+                    chunk = std::max<int64_t>(1, b->chunk_elems / std::max<int64_t>(per_tile, 1));
+                }
+            }
+            for (int64_t a0 = 0; a0 < total; a0 += chunk) {
+                BItem it{};
+                it.dom = which[wi];
+                it.type = sg.type;
+                it.axis = sg.axis;
+                it.in = sg.in;
+                it.out = sg.out;
+                it.a0 = a0;
+                it.a1 = std::min(total, a0 + chunk);
+                if (sg.type == ST_REDUCE) {
+                    it.slot = partials;
+                    partials += 2 * d.S;
+                }
+                per[wi][k].push_back(it);
+            }
+        }
+    }
+    // persistent mode: one counter per non-empty (domain, stage); an item
+    // waits for the previous non-empty stage of its domain
+    int64_t nc = 0;
+    for (size_t wi = 0; wi < which.size(); ++wi) {
+        int32_t prev = -1;
+        uint32_t prev_need = 0;
+        for (int k = 0; k < ns; ++k) {
+            if (per[wi][k].empty()) continue;
+            const int32_t c = (int32_t)nc++;
+            for (auto& it : per[wi][k]) {
+                it.done = c;
+                it.dep = prev;
+                it.need = prev_need;
+            }
+            prev = c;
+            prev_need = (uint32_t)per[wi][k].size();
+        }
+    }
+    // stage-major order; within a sweep stage grouped by (storage type, M)
+    for (int k = 0; k < ns; ++k) {
+        const Stage& sg = prog[k];
+        const bool sweep = sg.type == ST_SWEEP || sg.type == ST_SWEEP_T;
+        std::vector<std::pair<int, int>> classes;   // (dtype, M) in first-seen order
+        for (size_t wi = 0; wi < which.size(); ++wi) {
+            if (per[wi][k].empty()) continue;
+            const BDomain& d = b->doms[which[wi]];
+            const std::pair<int, int> c{d.dtype, sweep ? d.M[sg.axis] : 0};
+            if (std::find(classes.begin(), classes.end(), c) == classes.end()) classes.push_back(c);
+        }
+        for (const auto& c : classes) {
+            Launch L{};
+            L.sweep = sweep ? 1 : 0;
+            L.dtype = c.first;
+            L.M = c.second;
+            L.tr = sg.type == ST_SWEEP_T;
+            L.off = (int64_t)P.items.size();
+            for (size_t wi = 0; wi < which.size(); ++wi) {
+                const BDomain& d = b->doms[which[wi]];
+                if (sweep && (d.dtype != c.first || d.M[sg.axis] != c.second)) continue;
+                if (!sweep && d.dtype != c.first) continue;
+                for (auto& it : per[wi][k]) P.items.push_back(it);
+            }
+            L.count = (int64_t)P.items.size() - L.off;
+            if (L.count) P.launches.push_back(L);
+        }
+    }
+    P.ncounters = nc;
+    P.npartials = partials;
+}
+
+std::vector<Stage> forward_program()
+{
+    return {{ST_SRC, 0, 0, 0},   {ST_DIR, 0, 0, 0}, {ST_SWEEP, 0, 0, 0}, {ST_DIR, 0, 0, 0},
+            {ST_SWEEP, 1, 0, 0}, {ST_DIR, 0, 0, 0}, {ST_SWEEP, 2, 0, 0}, {ST_DIR, 0, 0, 0}};
+}
+
+// adjoint of one step: recompute the sweep outputs into buffers 2, 3, 4 from
+// the state in buffer 0, then run the transposed stages on the gradient (1)
+std::vector<Stage> adjoint_program()
+{
+    return {{ST_COPY, 0, 0, 2},    {ST_SRC, 0, 2, 2},     {ST_DIR, 0, 2, 2},   {ST_SWEEP, 0, 2, 2},
+            {ST_COPY, 0, 2, 3},    {ST_DIR, 0, 3, 3},     {ST_SWEEP, 1, 3, 3}, {ST_COPY, 0, 3, 4},
+            {ST_DIR, 0, 4, 4},     {ST_SWEEP, 2, 4, 4},   {ST_MASK, 0, 1, 1},  {ST_SWEEP_T, 2, 1, 1},
+            {ST_REDUCE, 2, 1, 4},  {ST_MASK, 0, 1, 1},    {ST_SWEEP_T, 1, 1, 1}, {ST_REDUCE, 1, 1, 3},
+            {ST_MASK, 0, 1, 1},    {ST_SWEEP_T, 0, 1, 1}, {ST_REDUCE, 0, 1, 2}, {ST_MASK, 0, 1, 1},
+            {ST_SRC_T, 0, 1, 1}};
+}
+
+// Counters that blocks of one launch use to hand work to each other must be
+// coherent across the GPU's XCDs while the kernel runs, so they are taken
+// from uncached device memory.  Uncached allocations are never freed (a
+// freed uncached block can corrupt later allocations): they come from a
+// grow-only, process-lifetime bump pool.  Persistent mode only.
+struct CounterPool {
+    uint32_t* chunk = nullptr;
+    size_t used = 0, cap = 0;
+};
+
+int counters_from_pool(int64_t n, uint32_t** out)
+{
+    static CounterPool pool;
+    const size_t need = ((size_t)n * sizeof(uint32_t) + 255) & ~(size_t)255;
+    if (!pool.chunk || pool.used + need > pool.cap) {
+        const size_t cap = std::max<size_t>(need, (size_t)4 << 20);
+        void* p = nullptr;
+        BHIP(hipExtMallocWithFlags(&p, cap, hipDeviceMallocUncached), "uncached counter allocation");
+        pool.chunk = static_cast<uint32_t*>(p);   // any previous chunk stays allocated
+        pool.used = 0;
+        pool.cap = cap;
+    }
+    *out = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(pool.chunk) + pool.used);
+    pool.used += need;
+    return BFVM_OK;
+}
+
+int ensure_counters(bfvm_batch b, int64_t n)
+{
+    if (b->counters_cap >= n) return BFVM_OK;
+    drop_graph(b->fwd);   // captured programs hold the old pointer
+    drop_graph(b->adj);
+    uint32_t* c = nullptr;
+    if (int st = counters_from_pool(n, &c)) return st;
+    b->d_counters = c;
+    b->counters_cap = n;
+    return BFVM_OK;
+}
+
+int upload_doms(bfvm_batch b)
+{
+    BHIP(hipMemcpyAsync(b->d_doms, b->doms.data(), sizeof(BDomain) * b->doms.size(), hipMemcpyHostToDevice,
+                        b->stream), "upload descriptors");
+    BHIP(hipStreamSynchronize(b->stream), "sync");
+    return BFVM_OK;
+}
+
+int upload_program(bfvm_batch b, Program& P)
+{
+    drop_graph(P);
+    if (P.d_items) (void)hipFree(P.d_items);
+    P.d_items = nullptr;
+    BHIP(hipMalloc((void**)&P.d_items, sizeof(BItem) * std::max<size_t>(1, P.items.size())), "hipMalloc items");
+    if (!P.items.empty())
+        BHIP(hipMemcpy(P.d_items, P.items.data(), sizeof(BItem) * P.items.size(), hipMemcpyHostToDevice),
+             "upload items");
+    if (b->mode == BFVM_BATCH_PERSISTENT) return ensure_counters(b, 2 + P.ncounters);
+    return BFVM_OK;
+}
+
+int build_forward(bfvm_batch b)
+{
+    // the tile plans, the chunk size or the mode may have changed: the
+    // adjoint program is rebuilt on its next call as well
+    free_program(b->adj);
+    b->adj_subset.clear();
+    std::vector<int32_t> all(b->doms.size());
+    for (size_t i = 0; i < all.size(); ++i) all[i] = (int32_t)i;
+    build_program(b, all, forward_program(), b->fwd);
+    return upload_program(b, b->fwd);
+}
+
+template <typename T, typename C, bool TR>
+void launch_group_sweep(int M, int64_t n, hipStream_t s, const BDomain* d, const BItem* it)
+{
+    const dim3 grid((unsigned)n), block(kBatchThreads);
+    switch (M) {
+        case 4: hipLaunchKernelGGL((k_group_sweep<T, C, 4, TR>), grid, block, 0, s, d, it); break;
+        case 8: hipLaunchKernelGGL((k_group_sweep<T, C, 8, TR>), grid, block, 0, s, d, it); break;
+        default: hipLaunchKernelGGL((k_group_sweep<T, C, 16, TR>), grid, block, 0, s, d, it); break;
+    }
+}
+
+// enqueue one run of a program on the batch stream
+int enqueue_program(bfvm_batch b, const Program& P)
+{
+    if (b->mode == BFVM_BATCH_PERSISTENT) {
+        const int64_t nreset = 2 + P.ncounters;
+        hipLaunchKernelGGL(k_batch_reset, dim3((unsigned)std::min<int64_t>((nreset + 255) / 256, 1024)), dim3(256),
+                           0, b->stream, b->d_counters, nreset);
+        BHIP(hipGetLastError(), "batch reset kernel");
+        hipLaunchKernelGGL(k_batch, dim3(b->blocks), dim3(kBatchThreads), 0, b->stream, b->d_doms, P.d_items,
+                           (int64_t)P.items.size(), b->d_counters, b->d_partials, b->wait_ticks);
+        BHIP(hipGetLastError(), "batch kernel");
+        return BFVM_OK;
+    }
+    for (const Launch& L : P.launches) {
+        const BItem* it = P.d_items + L.off;
+        if (!L.sweep) {
+            hipLaunchKernelGGL(k_group_sparse, dim3((unsigned)L.count), dim3(kBatchThreads), 0, b->stream,
+                               b->d_doms, it, b->d_partials);
+        } else if (L.dtype == BFVM_F64) {
+            if (L.tr) launch_group_sweep<double, double, true>(L.M, L.count, b->stream, b->d_doms, it);
+            else launch_group_sweep<double, double, false>(L.M, L.count, b->stream, b->d_doms, it);
+        } else if (L.dtype == BFVM_F32) {
+            if (L.tr) launch_group_sweep<float, double, true>(L.M, L.count, b->stream, b->d_doms, it);
+            else launch_group_sweep<float, double, false>(L.M, L.count, b->stream, b->d_doms, it);
+        } else {
+            if (L.tr) launch_group_sweep<float, float, true>(L.M, L.count, b->stream, b->d_doms, it);
+            else launch_group_sweep<float, float, false>(L.M, L.count, b->stream, b->d_doms, it);
+        }
+        BHIP(hipGetLastError(), "grouped stage kernel");
+    }
+    return BFVM_OK;
+}
+
+int capture(bfvm_batch b, Program& P)
+{
+    drop_graph(P);
+    BHIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    int st = enqueue_program(b, P);
+    hipGraph_t graph = nullptr;
+    hipError_t ee = hipStreamEndCapture(b->stream, &graph);
+    if (st) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (ee != hipSuccess) return bfail(BFVM_EDEVICE, std::string("end capture: ") + hipGetErrorString(ee));
+    P.graph = graph;
+    BHIP(hipGraphInstantiate(&P.exec, graph, nullptr, nullptr, 0), "graph instantiate");
+    return BFVM_OK;
+}
+
+// wait for the batch stream; in persistent mode also check the error flag
+int finish(bfvm_batch b)
+{
+    if (b->mode == BFVM_BATCH_PERSISTENT) {
+        uint32_t flag = 0;
+        BHIP(hipMemcpyAsync(&flag, b->d_counters + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, b->stream),
+             "read flag");
+        BHIP(hipStreamSynchronize(b->stream), "sync");
+        if (flag) return bfail(BFVM_EDEVICE, "batch dependency wait exceeded its time limit (2 s)");
+        return BFVM_OK;
+    }
+    BHIP(hipStreamSynchronize(b->stream), "sync");
+    return BFVM_OK;
+}
+
+int refresh_from_grids(bfvm_batch b)
+{
+    for (size_t i = 0; i < b->grids.size(); ++i) {
+        bfvm_grid g = b->grids[i];
+        BDomain& d = b->doms[i];
+        d.dtype = g->dtype;
+        d.S = g->S;
+        d.nx = g->nx;
+        d.ny = g->ny;
+        d.nz = g->nz;
+        const bool f32c = g->dtype == BFVM_F32_FAST;
+        for (int a = 0; a < 3; ++a) {
+            d.invd[a] = f32c ? (const void*)g->invd32[a] : (const void*)g->invd64[a];
+            d.r[a] = f32c ? (const void*)g->r32[a] : (const void*)g->r64[a];
+        }
+        d.src_vox = g->src_vox;
+        d.src_P = g->src_P;
+        d.src_invQ = g->src_invQ;
+        d.nsrc = g->nsrc;
+        d.dir_elem = g->dir_elem;
+        d.dir_val = g->dir_val;
+        d.ndir = g->ndir;
+    }
+    return BFVM_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+int bfvm_batch_create(bfvm_batch* out, int32_t ndomains, const bfvm_grid* grids, void* const* fields, void* stream)
+{
+    if (!out) return bfail(BFVM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (ndomains < 1 || !grids || !fields) return bfail(BFVM_EINVAL, "need >= 1 grid and field");
+    for (int32_t i = 0; i < ndomains; ++i) {
+        if (!grids[i] || !fields[i]) return bfail(BFVM_EINVAL, "NULL grid or field");
+        if (!grids[i]->have_params) return bfail(BFVM_ESTATE, "every grid needs set_params first");
+        for (int a = 0; a < 3; ++a) {
+            const int64_t n = a == 0 ? grids[i]->nx : (a == 1 ? grids[i]->ny : grids[i]->nz);
+            if (n > kMaxBatchLine) return bfail(BFVM_EINVAL, "batched domains support line lengths up to 256");
+        }
+    }
+    bfvm_batch b = new (std::nothrow) bfvm_batch_s();
+    if (!b) return bfail(BFVM_ENOMEM, "host allocation failed");
+    b->stream = static_cast<hipStream_t>(stream);
+    if (!b->stream) {   // the legacy null stream cannot be captured into a graph
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete b;
+            return bfail(BFVM_EDEVICE, "hipStreamCreateWithFlags");
+        }
+        b->own_stream = true;
+    }
+    b->grids.assign(grids, grids + ndomains);
+    b->doms.resize(ndomains);
+    std::memset(b->doms.data(), 0, sizeof(BDomain) * ndomains);
+    refresh_from_grids(b);
+    for (int32_t i = 0; i < ndomains; ++i) {
+        b->doms[i].buf[0] = fields[i];
+        default_batch_plan(b->doms[i], b->mode);
+    }
+    int dev = 0, cus = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, kBatchThreads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    b->blocks = cus * per_cu;
+    int rate_khz = 0;   // wall_clock64() frequency
+    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || rate_khz <= 0)
+        rate_khz = 100000;
+    b->wait_ticks = (uint64_t)rate_khz * 1000ull * 2ull;   // 2 s per dependency wait
+    int st = BFVM_OK;
+    hipError_t e = hipMalloc((void**)&b->d_doms, sizeof(BDomain) * ndomains);
+    if (e != hipSuccess) st = bfail(BFVM_ENOMEM, "hipMalloc descriptors");
+    if (!st) st = upload_doms(b);
+    if (!st) st = build_forward(b);
+    if (st) {
+        bfvm_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return BFVM_OK;
+}
+
+int bfvm_batch_destroy(bfvm_batch b)
+{
+    if (!b) return BFVM_OK;
+    (void)hipStreamSynchronize(b->stream);
+    free_program(b->fwd);
+    free_program(b->adj);
+    if (b->d_doms) (void)hipFree(b->d_doms);
+    if (b->d_partials) (void)hipFree(b->d_partials);
+    // d_counters is a slice of the uncached pool: never freed
+    if (b->work_mem) (void)hipFree(b->work_mem);
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return BFVM_OK;
+}
+
+int bfvm_batch_set_mode(bfvm_batch b, int32_t mode)
+{
+    if (!b) return bfail(BFVM_EINVAL, "batch is NULL");
+    if (mode != BFVM_BATCH_GROUPED && mode != BFVM_BATCH_PERSISTENT) return bfail(BFVM_EINVAL, "unknown mode");
+    if (mode == BFVM_BATCH_PERSISTENT && !kPersistentModeEnabled)
+        return bfail(BFVM_EOFF, "the single-launch persistent mode is switched off: its cross-block "
+                                "dependency waits did not complete on gfx950");
+    if (mode == b->mode) return BFVM_OK;
+    b->mode = mode;
+    for (auto& d : b->doms) default_batch_plan(d, mode);
+    if (int st = upload_doms(b)) return st;
+    return build_forward(b);
+}
+
+int bfvm_batch_set_fields(bfvm_batch b, int32_t which, void* const* ptrs)
+{
+    if (!b) return bfail(BFVM_EINVAL, "batch is NULL");
+    if ((which != 0 && which != 1) || !ptrs) return bfail(BFVM_EINVAL, "which must be 0 (field) or 1 (gradient)");
+    for (size_t i = 0; i < b->doms.size(); ++i)
+        if (which == 0 && !ptrs[i]) return bfail(BFVM_EINVAL, "NULL field");
+    for (size_t i = 0; i < b->doms.size(); ++i) b->doms[i].buf[which] = ptrs[i];
+    return upload_doms(b);
+}
+
+int bfvm_batch_step(bfvm_batch b, int64_t nsteps)
+{
+    if (!b) return bfail(BFVM_EINVAL, "batch is NULL");
+    if (nsteps < 0) return bfail(BFVM_EINVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return BFVM_OK;
+    if (!b->fwd.exec)
+        if (int st = capture(b, b->fwd)) return st;
+    for (int64_t t = 0; t < nsteps; ++t) BHIP(hipGraphLaunch(b->fwd.exec, b->stream), "graph launch");
+    return finish(b);
+}
+
+int bfvm_batch_step_eager(bfvm_batch b, int64_t nsteps)
+{
+    if (!b) return bfail(BFVM_EINVAL, "batch is NULL");
+    if (nsteps < 0) return bfail(BFVM_EINVAL, "nsteps must be >= 0");
+    for (int64_t t = 0; t < nsteps; ++t)
+        if (int st = enqueue_program(b, b->fwd)) return st;
+    return finish(b);
+}
+
+int bfvm_batch_step_adjoint(bfvm_batch b, int32_t count, const int32_t* subset, double* grad_D, double* grad_lambda)
+{
+    if (!b) return bfail(BFVM_EINVAL, "batch is NULL");
+    if (count < 1 || !subset || !grad_D || !grad_lambda) return bfail(BFVM_EINVAL, "bad subset or NULL");
+    for (int32_t i = 0; i < count; ++i) {
+        if (subset[i] < 0 || subset[i] >= (int32_t)b->doms.size()) return bfail(BFVM_ERANGE, "domain index");
+        if (!b->doms[subset[i]].buf[1]) return bfail(BFVM_ESTATE, "set the gradient buffers first");
+        for (int32_t j = 0; j < i; ++j)
+            if (subset[j] == subset[i]) return bfail(BFVM_EINVAL, "repeated domain in subset");
+    }
+    std::vector<int32_t> sub(subset, subset + count);
+    if (sub != b->adj_subset || !b->adj.exec) {
+        // (re)build the adjoint program: workspace, items, partials, graph
+        free_program(b->adj);
+        b->adj_subset.clear();
+        if (b->work_mem) (void)hipFree(b->work_mem);
+        b->work_mem = nullptr;
+        size_t total = 0;
+        std::vector<size_t> off(count);
+        for (int32_t i = 0; i < count; ++i) {
+            const BDomain& d = b->doms[sub[i]];
+            off[i] = total;
+            total += 3 * (size_t)(d.nx * d.ny * d.nz * d.S) * dtype_size(d.dtype);
+            total = (total + 255) & ~(size_t)255;
+        }
+        BHIP(hipMalloc(&b->work_mem, total), "hipMalloc adjoint workspace");
+        for (int32_t i = 0; i < count; ++i) {
+            BDomain& d = b->doms[sub[i]];
+            const size_t nb = (size_t)(d.nx * d.ny * d.nz * d.S) * dtype_size(d.dtype);
+            for (int k = 0; k < 3; ++k) d.buf[2 + k] = static_cast<char*>(b->work_mem) + off[i] + k * nb;
+        }
+        if (int st = upload_doms(b)) return st;
+        build_program(b, sub, adjoint_program(), b->adj);
+        if (b->partials_cap < b->adj.npartials) {
+            drop_graph(b->fwd);   // the forward graph holds the old partials pointer
+            if (b->d_partials) (void)hipFree(b->d_partials);
+            b->d_partials = nullptr;
+            BHIP(hipMalloc((void**)&b->d_partials, sizeof(double) * std::max<int64_t>(1, b->adj.npartials)),
+                 "hipMalloc partials");
+            b->partials_cap = b->adj.npartials;
+        }
+        if (int st = upload_program(b, b->adj)) return st;
+        if (int st = capture(b, b->adj)) return st;
+        b->adj_subset = sub;
+    }
+    BHIP(hipGraphLaunch(b->adj.exec, b->stream), "graph launch");
+    if (int st = finish(b)) return st;
+    std::vector<double> part(b->adj.npartials);
+    if (!part.empty())
+        BHIP(hipMemcpy(part.data(), b->d_partials, sizeof(double) * part.size(), hipMemcpyDeviceToHost),
+             "read partials");
+    // per domain of the subset (in subset order), per axis: sums in item order
+    std::map<int32_t, int> pos;
+    int64_t base = 0;
+    std::vector<int64_t> first(count);
+    for (int32_t i = 0; i < count; ++i) {
+        pos[sub[i]] = i;
+        first[i] = base;
+        base += b->doms[sub[i]].S;
+    }
+    std::vector<double> Gr(base * 3, 0.0), Gb(base * 3, 0.0);
+    for (const BItem& it : b->adj.items) {
+        if (it.type != ST_REDUCE) continue;
+        const int i = pos[it.dom];
+        const int S = b->doms[it.dom].S;
+        for (int s = 0; s < S; ++s) {
+            Gr[(first[i] + s) * 3 + it.axis] += part[it.slot + 2 * s + 0];
+            Gb[(first[i] + s) * 3 + it.axis] += part[it.slot + 2 * s + 1];
+        }
+    }
+    for (int32_t i = 0; i < count; ++i) {
+        bfvm_grid g = b->grids[sub[i]];
+        for (int s = 0; s < g->S; ++s)
+            for (int a = 0; a < 3; ++a) {
+                grad_D[first[i] + s] += -Gr[(first[i] + s) * 3 + a] * g->dt / (g->h[a] * g->h[a]);
+                grad_lambda[first[i] + s] += -Gb[(first[i] + s) * 3 + a] * g->dt / 3.0;
+            }
+    }
+    return BFVM_OK;
+}
+
+int bfvm_batch_get_plan(bfvm_batch b, int32_t domain, int32_t axis, int32_t* m, int32_t* lpw)
+{
+    if (!b || !m || !lpw) return bfail(BFVM_EINVAL, "NULL");
+    if (domain < 0 || domain >= (int32_t)b->doms.size() || axis < 0 || axis > 2)
+        return bfail(BFVM_ERANGE, "domain or axis");
+    *m = b->doms[domain].M[axis];
+    *lpw = b->doms[domain].lpw[axis];
+    return BFVM_OK;
+}
+
+int bfvm_batch_info(bfvm_batch b, int64_t* items, int32_t* launches, int64_t* chunk_elems)
+{
+    if (!b || !items || !launches || !chunk_elems) return bfail(BFVM_EINVAL, "NULL");
+    *items = (int64_t)b->fwd.items.size();
+    *launches = b->mode == BFVM_BATCH_PERSISTENT ? 2 : (int32_t)b->fwd.launches.size();
+    *chunk_elems = b->chunk_elems;
+    return BFVM_OK;
+}
+
+}  // extern "C"
+
+// ================================================================ autotuner
+//
+// Tunes, for the batch at hand, (1) the tile shape of every (axis, line
+// length, substrate count, storage type) class: lines per tile lpw in
+// {16, 32, 64} with the smallest elements-per-thread M in {4, 8, 16} that
+// still covers the line (K = 512 / lpw segments of M), and (2) the work
+// per item.  Coordinate descent: for each axis, each lpw candidate is
+// applied to every domain where it fits and the whole batch step is timed;
+// then each chunk size.  Results are cached in a small JSON file keyed by
+// the GPU architecture and the class, and reused when every class of the
+// batch is present.
+
+namespace {
+
+std::string class_key(const BDomain& d, int axis)
+{
+    std::ostringstream o;
+    o << axis << ":" << axis_len(d, axis) << ":" << d.S << ":" << d.dtype;
+    return o.str();
+}
+
+double time_steps(bfvm_batch b, int reps, int* st)
+{
+    hipEvent_t e0, e1;
+    *st = BFVM_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        *st = bfail(BFVM_EDEVICE, "event create");
+        return 1e30;
+    }
+    *st = enqueue_program(b, b->fwd);   // warm-up
+    (void)hipEventRecord(e0, b->stream);
+    for (int r = 0; r < reps && !*st; ++r) *st = enqueue_program(b, b->fwd);
+    (void)hipEventRecord(e1, b->stream);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!*st) *st = finish(b);
+    return ms / reps;
+}
+
+// minimal JSON cache: {"arch": "...", "chunk": N, "plans": {"key": [M, lpw], ...}}
+bool load_cache(const std::string& path, const std::string& arch, int64_t* chunk,
+                std::map<std::string, std::pair<int, int>>* plans)
+{
+    std::ifstream f(path);
+    if (!f) return false;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string t = ss.str();
+    if (t.find("\"arch\": \"" + arch + "\"") == std::string::npos) return false;
+    size_t c = t.find("\"chunk\": ");
+    if (c == std::string::npos) return false;
+    *chunk = std::atoll(t.c_str() + c + 9);
+    size_t p = t.find("\"plans\": {");
+    if (p == std::string::npos) return false;
+    p += 10;
+    while (true) {
+        const size_t q0 = t.find('"', p);
+        if (q0 == std::string::npos) break;
+        const size_t q1 = t.find('"', q0 + 1);
+        const size_t b0 = t.find('[', q1);
+        const size_t b1 = t.find(']', b0);
+        if (q1 == std::string::npos || b0 == std::string::npos || b1 == std::string::npos) break;
+        int m = 0, l = 0;
+        if (std::sscanf(t.c_str() + b0, "[%d, %d]", &m, &l) == 2) (*plans)[t.substr(q0 + 1, q1 - q0 - 1)] = {m, l};
+        p = b1 + 1;
+    }
+    return *chunk > 0;
+}
+
+void save_cache(const std::string& path, const std::string& arch, int64_t chunk,
+                const std::map<std::string, std::pair<int, int>>& plans)
+{
+    std::ofstream f(path);
+    if (!f) return;
+    f << "{\"arch\": \"" << arch << "\", \"chunk\": " << chunk << ", \"plans\": {";
+    bool first = true;
+    for (auto& kv : plans) {
+        f << (first ? "" : ", ") << "\"" << kv.first << "\": [" << kv.second.first << ", " << kv.second.second << "]";
+        first = false;
+    }
+    f << "}}\n";
+}
+
+bool plan_ok(int mode, int64_t n, int m, int lpw)
+{
+    bool known_m = false;
+    for (int k : kBatchM) known_m |= (k == m && m <= max_m_for_mode(mode));
+    return known_m && (lpw == 16 || lpw == 32 || lpw == 64) && plan_fits(n, m, lpw);
+}
+
+}  // namespace
+
+extern "C" int bfvm_batch_autotune(bfvm_batch b, const char* cache_path, double* best_ms)
+{
+    if (!b || !best_ms) return bfail(BFVM_EINVAL, "NULL");
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    arch += b->mode == BFVM_BATCH_PERSISTENT ? "/persistent" : "/grouped";
+    std::map<std::string, std::pair<int, int>> cached;
+    int64_t chunk = 0;
+    int st = BFVM_OK;
+    if (cache_path && load_cache(cache_path, arch, &chunk, &cached)) {
+        bool all = true;
+        for (auto& d : b->doms)
+            for (int a = 0; a < 3; ++a) {
+                auto it = cached.find(class_key(d, a));
+                if (it == cached.end() || !plan_ok(b->mode, axis_len(d, a), it->second.first, it->second.second))
+                    all = false;
+            }
+        if (all) {
+            for (auto& d : b->doms)
+                for (int a = 0; a < 3; ++a) {
+                    const auto pl = cached[class_key(d, a)];
+                    d.M[a] = pl.first;
+                    d.lpw[a] = pl.second;
+                }
+            b->chunk_elems = chunk;
+            if ((st = upload_doms(b)) || (st = build_forward(b))) return st;
+            *best_ms = time_steps(b, 3, &st);
+            return st;
+        }
+    }
+    if ((st = build_forward(b))) return st;
+    double best = time_steps(b, 3, &st);
+    if (st) return st;
+    const int lps[] = {16, 32, 64};
+    for (int a = 0; a < 3; ++a) {
+        std::vector<BDomain> keep = b->doms;
+        for (int l : lps) {
+            std::vector<BDomain> trial = keep;
+            for (auto& d : trial) {
+                const int m = smallest_m(axis_len(d, a), l, max_m_for_mode(b->mode));
+                if (m) {
+                    d.M[a] = m;
+                    d.lpw[a] = l;
+                }
+            }
+            b->doms = trial;
+            if ((st = upload_doms(b)) || (st = build_forward(b))) return st;
+            const double t = time_steps(b, 3, &st);
+            if (st) return st;
+            if (t < best) {
+                best = t;
+                keep = trial;
+            }
+        }
+        b->doms = keep;
+    }
+    const int64_t chunks[] = {1 << 12, 1 << 13, 1 << 14, 1 << 15, 1 << 16, 1 << 17};
+    int64_t best_chunk = b->chunk_elems;
+    for (int64_t c : chunks) {
+        b->chunk_elems = c;
+        if ((st = upload_doms(b)) || (st = build_forward(b))) return st;
+        const double t = time_steps(b, 3, &st);
+        if (st) return st;
+        if (t < best) {
+            best = t;
+            best_chunk = c;
+        }
+    }
+    b->chunk_elems = best_chunk;
+    if ((st = upload_doms(b)) || (st = build_forward(b))) return st;
+    if (cache_path) {
+        for (auto& d : b->doms)
+            for (int a = 0; a < 3; ++a) cached[class_key(d, a)] = {d.M[a], d.lpw[a]};
+        save_cache(cache_path, arch, best_chunk, cached);
+    }
+    *best_ms = best;
+    return BFVM_OK;
+}

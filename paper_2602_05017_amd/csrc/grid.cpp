@@ -364,6 +364,7 @@ const char* bfvm_status_string(int status)
         case BFVM_ESTATE: return "call out of order";
         case BFVM_EDEVICE: return "HIP device error";
         case BFVM_ENOMEM: return "out of memory";
+        case BFVM_EOFF: return "feature switched off";
         default: return "unknown status";
     }
 }

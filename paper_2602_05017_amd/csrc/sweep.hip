@@ -29,6 +29,7 @@
 //   k_sweep_seg_xtile    x: rows of nx*S contiguous elements staged through
 //                        LDS (coalesced load/store), lanes over segments
 #include "internal.hpp"
+#include "seg_solver.hpp"
 
 #include <algorithm>
 
@@ -118,209 +119,12 @@ __global__ __launch_bounds__(256) void k_sweep_line(const T* in, T* out, AxisGeo
     }
 }
 
-// ------------------------------------------------ segment solver (registers)
-//
-// Shared by both segmented kernels.  v[0..cnt) holds the segment's inputs
-// (elements i0 .. i0+cnt-1 of line `line`, substrate s); on return it holds
-// the final solution.  sc points to 4 LDS arrays of [K][nl] values (forward
-// local value, forward coefficient product, backward local value, backward
-// coefficient product), indexed [segment * nl + line].  Every thread of the
-// block must call this (it contains barriers); threads without a valid
-// segment pass cnt = 0, threads without a line pass writer = false.
-//
-// The carries are resolved by one leader thread per line (threads 0..nl-1),
-// which walks the K segments in order with all LDS loads issued ahead of
-// the dependent multiply-add chain, and leaves each segment's incoming carry
-// in place of its local value.
-
-template <typename C>
-__device__ __forceinline__ void carry_scan(C* val, const C* prod, int K, int nl, int line, bool reverse)
-{
-    C c = 0;
-    if (!reverse) {
-        int j = 0;
-        for (; j + 8 <= K; j += 8) {
-            C f[8], g[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) { f[u] = val[(j + u) * nl + line]; g[u] = prod[(j + u) * nl + line]; }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) { val[(j + u) * nl + line] = c; c = f[u] + g[u] * c; }
-        }
-        for (; j < K; ++j) {
-            const C f = val[j * nl + line], g = prod[j * nl + line];
-            val[j * nl + line] = c;
-            c = f + g * c;
-        }
-    } else {
-        int j = K - 1;
-        for (; j - 8 >= -1; j -= 8) {
-            C f[8], g[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) { f[u] = val[(j - u) * nl + line]; g[u] = prod[(j - u) * nl + line]; }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) { val[(j - u) * nl + line] = c; c = f[u] + g[u] * c; }
-        }
-        for (; j >= 0; --j) {
-            const C f = val[j * nl + line], g = prod[j * nl + line];
-            val[j * nl + line] = c;
-            c = f + g * c;
-        }
-    }
-}
-
-// Ragged tails.  A line of n elements is covered by K segments of M; the
-// slots past the end (i >= n) are padding: their coefficient invd is 0 and
-// their input is any finite value (a clamped, in-bounds load).  With invd = 0
-// a padding slot yields exactly 0 in both passes and multiplies every carry
-// crossing it by 0, so it changes no real element, in the Thomas solve and
-// in the transposed solve alike.  Every segment therefore runs the same
-// guard-free code; only the final stores are guarded.
-
-// Coefficient accessors: coef(k) = invd of slot i0 + k of the thread's
-// segment (0 when i0 + k >= n), prev = invd of slot i0 - 1 (0 when i0 = 0).
-template <typename C>
-struct LdsCoef {        // the block's zero-padded LDS copy, [s][segment][k] layout
-    const C* p;                // &tab[s*SP + seg*MP]: the M slots are contiguous
-    C prev;
-    __device__ __forceinline__ C operator()(int k) const { return p[k]; }
-};
-
-template <typename C>
-struct GlobalCoef {     // the global [n][S] table, masked past the line end
-    const C* __restrict__ p;   // &invd[i0*S + s] (clamped into the table)
-    int S;
-    int last;                  // n - 1 - i0
-    C prev;
-    __device__ __forceinline__ C operator()(int k) const
-    {
-        return k <= last ? p[(k <= last ? k : 0) * S] : (C)0;
-    }
-};
-
-template <typename C, int M>
-struct RegCoef {        // the segment's M values held in registers
-    C b[M];
-    C prev;
-    __device__ __forceinline__ C operator()(int k) const { return b[k]; }
-};
-
-// The three register phases of a segment.
-// forward pass with zero carry; G = product of the forward coefficients
-template <typename C, int M, bool TR, typename Coef>
-__device__ __forceinline__ void seg_forward(C (&v)[M], C r, const Coef& coef, C& f, C& G)
-{
-    f = 0;
-    G = 1;
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-        const C b = coef(k);
-        if (!TR) {
-            f = b * (v[k] + r * f);
-            G *= r * b;
-        } else {
-            const C a = r * (k > 0 ? coef(k - 1) : coef.prev);
-            f = v[k] + a * f;
-            G *= a;
-        }
-        v[k] = f;
-    }
-}
-
-// forward correction t_i = f_i + (prod of coefficients up to i) * carry, then
-// the backward pass with zero carry; GB = product of alpha over the segment
-template <typename C, int M, bool TR, typename Coef>
-__device__ __forceinline__ void seg_middle(C (&v)[M], C r, const Coef& coef, C carry, C& bw, C& GB)
-{
-    C c = carry;
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-        const C a = r * (!TR ? coef(k) : (k > 0 ? coef(k - 1) : coef.prev));
-        c = a * c;
-        v[k] += c;
-    }
-    // Re-read the coefficients below instead of keeping all M of them live
-    // across both loops (they are cheap LDS/L1 reads; registers are not).
-    asm volatile("" ::: "memory");
-    bw = 0;
-    GB = 1;
-#pragma unroll
-    for (int k = M - 1; k >= 0; --k) {
-        const C b = coef(k);
-        const C a = r * b;
-        if (!TR)
-            bw = v[k] + a * bw;
-        else
-            bw = b * (v[k] + r * bw);
-        GB *= a;
-        v[k] = bw;
-    }
-}
-
-// backward correction x_i = b_i + (prod of alpha from i to the segment end) * X
-template <typename C, int M, typename Coef>
-__device__ __forceinline__ void seg_last(C (&v)[M], C r, const Coef& coef, C X)
-{
-    C e = X;
-#pragma unroll
-    for (int k = M - 1; k >= 0; --k) {
-        e = r * coef(k) * e;
-        v[k] += e;
-    }
-}
-
-// Solve one segment held in v (see the file comment).  sc points to 4 LDS
-// arrays of [K][nl] carry terms indexed [segment * nl + line].  Every thread
-// of the block calls this (it holds barriers); writer = the thread owns a
-// (segment, line) slot.
-template <typename C, int M, bool TR, typename Coef>
-__device__ __forceinline__ void solve_segment(C (&v)[M], int seg, int K, int line, int nl, C r,
-                                              const Coef& coef, C* sc, bool writer)
-{
-    C* sF = sc;
-    C* sG = sc + K * nl;
-    C* sB = sc + 2 * K * nl;
-    C* sH = sc + 3 * K * nl;
-    const int slot = seg * nl + line;
-    C f, G;
-    seg_forward<C, M, TR>(v, r, coef, f, G);
-    if (writer) {
-        sF[slot] = f;
-        sG[slot] = G;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < nl) carry_scan(sF, sG, K, nl, threadIdx.x, false);
-    __syncthreads();
-    const C carry = writer ? sF[slot] : (C)0;
-    C bw, GB;
-    seg_middle<C, M, TR>(v, r, coef, carry, bw, GB);
-    if (writer) {
-        sB[slot] = bw;
-        sH[slot] = GB;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < nl) carry_scan(sB, sH, K, nl, threadIdx.x, true);
-    __syncthreads();
-    const C X = writer ? sB[slot] : (C)0;
-    seg_last<C, M>(v, r, coef, X);
-}
-
 // --------------------------------------------------- kind 1 (strided, y / z)
 //
 // Block = lpw neighbouring lines x K segments; blockDim = K * lpw.  Lane l of
 // wave w handles line (l % lpw) and segment (w * (64/lpw) + l / lpw), so a
 // wave's load of element k touches 64/lpw runs of lpw consecutive elements.
 // blockIdx.x: line tile, blockIdx.y: outer index.
-
-template <typename T> struct Vec16;
-template <> struct Vec16<double> { using type = double2; };
-template <> struct Vec16<float> { using type = float4; };
-
-struct FastDiv {   // q / d for q * d <= 2^40: (q * m) >> 40
-    uint64_t m;
-    __host__ __device__ FastDiv() : m(1) {}
-    __host__ __device__ explicit FastDiv(uint32_t d) : m(((1ull << 40) + d - 1) / d) {}
-    __device__ __forceinline__ uint32_t div(uint32_t q) const { return (uint32_t)(((uint64_t)q * m) >> 40); }
-};
 
 // Copy the [n][S] coefficient table into LDS for K*M slots in [s][seg][k]
 // layout: slot (i, s) at s*SP + (i/M)*MP + i%M, with MP = M + 1 and SP chosen

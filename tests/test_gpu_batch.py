@@ -1,0 +1,168 @@
+"""Batched multi-domain form: uneven domains (each axis 24..192 voxels, 1..8
+substrates, FP32/FP64 storage mixed) stepped together, one graph replay per
+step.  Every domain is compared with the FP64 oracle at its storage type's
+bar and with its own single-grid GPU run within the same bar (the batch
+reads the Thomas constants from the global tables instead of LDS, which
+can change the rounding of individual products only through operation
+order, so equality is not required); graph replays must equal eager
+launches exactly.
+
+Modes.  "grouped" (one launch per stage over all domains) is the library's
+default.  "persistent" (one launch per step, blocks waiting on per-stage
+counters) hung on gfx950 twice and is switched off in the library (its mode
+switch returns EOFF); its cases stay here, skipped, until the cause of the
+hang is shown.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_helpers import make_grid, oracle_lists, rel_err, upload
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "f32fast": 1e-4}
+
+_PERSISTENT_OFF = ("persistent single-launch mode switched off: its cross-block dependency waits "
+                   "did not complete on gfx950 (hung twice); not run until the cause is shown")
+MODES = ["grouped", pytest.param("persistent", marks=pytest.mark.skip(reason=_PERSISTENT_OFF))]
+
+
+def _domains(n, lo=24, hi=64, nsteps=3, seed=1005):
+    return workloads.batch_config(n_domains=n, lo=lo, hi=hi, nsteps=nsteps, seed=seed)
+
+
+def _setup(probs):
+    grids = [make_grid(p, p.dtype) for p in probs]
+    fields = [upload(p, g) for p, g in zip(probs, grids)]
+    return grids, fields
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_matches_oracle_per_domain_and_graph_equals_eager(mode):
+    import torch
+    import paper_2602_05017_amd as bf
+    probs = _domains(12, nsteps=3)
+    # add Dirichlet entries to a few domains so every stage type is exercised
+    for k in (1, 4, 7):
+        probs[k].dr = workloads.dirichlet_variant(probs[k], 9)
+    grids, fields = _setup(probs)
+    b = bf.Batch(grids, fields, mode=mode)
+    b.step(3, graph=True)
+    got = [g.read_field(f) for g, f in zip(grids, fields)]
+    for p, out in zip(probs, got):
+        u = np.array(p.u0, copy=True)
+        src, dr = oracle_lists(p)
+        oracle.step(u, p.h, p.D, p.lam, p.dt, src, dr, 3)
+        assert rel_err(out, u)[0] <= TOL[p.dtype], p.name
+    # replay vs eager: same launches, same results, every replay checked
+    grids2, fields2 = _setup(probs)
+    b2 = bf.Batch(grids2, fields2, mode=mode)
+    b2.step(3, graph=False)
+    for rep in range(3):
+        b.step(1, graph=True)
+        b2.step(1, graph=False)
+        torch.cuda.synchronize()
+        for f1, f2 in zip(fields, fields2):
+            assert torch.equal(f1, f2), rep
+        # eager work and a sync between replays
+        _ = [f.sum().item() for f in fields[:2]]
+    b.close()
+    b2.close()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_equals_single_grid_steps(mode):
+    import torch
+    import paper_2602_05017_amd as bf
+    probs = _domains(8, lo=24, hi=192, nsteps=4, seed=1006)
+    grids, fields = _setup(probs)
+    b = bf.Batch(grids, fields, mode=mode)
+    info = b.info()
+    assert info["items"] > 0 and info["launches"] >= 3
+    b.step(4)
+    batched = [g.read_field(f) for g, f in zip(grids, fields)]
+    b.close()
+    for p, out in zip(probs, batched):
+        single = make_grid(p, p.dtype)
+        u = upload(p, single)
+        single.step(u, 4)
+        torch.cuda.synchronize()
+        ref = single.read_field(u)
+        single.close()
+        assert rel_err(out, ref)[0] <= TOL[p.dtype], p.name
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_autotuner_picks_valid_plans_and_keeps_results(tmp_path, mode):
+    import torch
+    import paper_2602_05017_amd as bf
+    probs = _domains(10, lo=24, hi=192, nsteps=2, seed=1007)
+    grids, fields = _setup(probs)
+    b = bf.Batch(grids, fields, mode=mode)
+    cache = str(tmp_path / "tune.json")
+    ms = b.autotune(cache)
+    assert ms > 0
+    for d, p in enumerate(probs):
+        for a, n in enumerate((p.nx, p.ny, p.nz)):
+            m, lpw = b.plan(d, a)
+            assert m in (4, 8, 16) and lpw in (16, 32, 64) and (512 // lpw) * m >= n
+    # autotuning ran steps on the fields: reload them, then step and compare
+    for p, g, f in zip(probs, grids, fields):
+        f.copy_(upload(p, g))
+    torch.cuda.synchronize()
+    b.step(2)
+    for p, g, f in zip(probs, grids, fields):
+        u = np.array(p.u0, copy=True)
+        src, dr = oracle_lists(p)
+        oracle.step(u, p.h, p.D, p.lam, p.dt, src, dr, 2)
+        assert rel_err(g.read_field(f), u)[0] <= TOL[p.dtype], p.name
+    # a second batch with the same classes reuses the cache
+    ms2 = b.autotune(cache)
+    assert ms2 > 0
+    b.close()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_adjoint_subset_matches_single_grid_adjoint(mode):
+    import torch
+    import paper_2602_05017_amd as bf
+    probs = _domains(9, lo=24, hi=64, nsteps=1, seed=1008)
+    probs[2].dr = workloads.dirichlet_variant(probs[2], 7)
+    grids, fields = _setup(probs)
+    rng = np.random.default_rng(9)
+    grads = [torch.from_numpy(rng.random(p.shape) - 0.5).to(device="cuda", dtype=g.torch_dtype)
+             for p, g in zip(probs, grids)]
+    gin = [x.clone() for x in grads]
+    b = bf.Batch(grids, fields, mode=mode)
+    b.set_grads(grads)
+    subset = [0, 2, 5, 8]
+    gD, gL = b.step_adjoint(subset)
+    off = 0
+    for i in subset:
+        p, g = probs[i], grids[i]
+        ref_g = gin[i].clone()
+        rD, rL = g.step_adjoint(fields[i], ref_g)
+        tol = TOL[p.dtype]
+        assert rel_err(grads[i].double().cpu().numpy(), ref_g.double().cpu().numpy())[0] <= tol
+        S = p.S
+        assert np.max(np.abs(gD[off:off + S] - rD) / np.abs(rD)) <= max(tol, 1e-11)
+        assert np.max(np.abs(gL[off:off + S] - rL) / np.abs(rL)) <= max(tol, 1e-11)
+        off += S
+    # domains outside the subset keep their gradients
+    for i in set(range(9)) - set(subset):
+        assert torch.equal(grads[i], gin[i])
+    # a second call on the same subset replays the captured graph
+    gD2, gL2 = b.step_adjoint(subset)
+    assert np.all(np.isfinite(gD2)) and np.all(np.isfinite(gL2))
+    b.close()
+
+
+def test_persistent_mode_is_refused():
+    import paper_2602_05017_amd as bf
+    probs = _domains(2, nsteps=1, seed=1009)
+    grids, fields = _setup(probs)
+    with pytest.raises(bf.BfvmError) as ei:
+        bf.Batch(grids, fields, mode="persistent")
+    assert ei.value.code == "EOFF"
