@@ -7,6 +7,11 @@ lambda in [0.01, 0.1] /min, dt = 0.01 min, 1e6 source/sink voxels; the
 paper's "8% liver" cube (Table 1) at 10 um resolution.  One step = Src,
 Dir x4 (none in this workload), x, y and z Thomas sweeps.
 
+--workload batch: 96 independent domains (each axis uniform in 24..192
+voxels, 1..8 substrates, FP32 or FP64 storage by a seeded coin, 1% of the
+voxels as sources), autotuned, stepped together by one graph replay per step
+(100 steps), plus the reverse step of domains 0..31.
+
 Prints ONE JSON line: voxel-substrate updates/s per LOD step, the roofline
 of the dominant kernel (algorithmic HBM bytes per launch / its mean launch
 time from HIP events on the grid's stream, against the 8 TB/s HBM peak),
@@ -39,9 +44,12 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 20; 100 for the batch workload)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="liver", choices=["liver", "cells", "gaussian"])
+    ap.add_argument("--workload", default="liver", choices=["liver", "cells", "gaussian", "batch"])
+    ap.add_argument("--adjoint-steps", type=int, default=5,
+                    help="batch workload: timed reverse steps of the 32-domain subset")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-storage companion run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=1)
@@ -153,6 +161,95 @@ def cpu_baseline(p, sample_steps):
                       f"({upd:.3g} voxel-substrate updates, {t:.2f} s)"}
 
 
+def run_batch(args):
+    """The batched form: every domain's step in one graph replay."""
+    import torch
+    import workloads
+    import paper_2602_05017_amd as bf
+    steps = 100 if args.steps is None else args.steps
+    probs = workloads.batch_config()
+    nsub = sum(p.S for p in probs)
+    upd = sum(p.V * p.S for p in probs)
+    alg = sum(p.V * p.S * (3 * 2 * (8 if p.dtype == "f64" else 4)) for p in probs)
+    n64 = sum(p.dtype == "f64" for p in probs)
+    log(f"batch: {len(probs)} domains ({n64} f64, {len(probs) - n64} f32), {upd:.4g} voxel-substrates, "
+        f"{alg / 1e9:.2f} GB algorithmic traffic per step")
+    grids = [make_grid(p, p.dtype) for p in probs]
+    hosts = [torch.from_numpy(p.u0) for p in probs]
+    fields = [torch.empty(p.shape, dtype=g.torch_dtype, device="cuda") for p, g in zip(probs, grids)]
+
+    def reload():
+        for f, h in zip(fields, hosts):
+            f.copy_(h)
+        torch.cuda.synchronize()
+
+    reload()
+    b = bf.Batch(grids, fields)
+    t0 = time.perf_counter()
+    tuned_ms = b.autotune(None)
+    log(f"autotuned in {time.perf_counter() - t0:.1f} s: {tuned_ms:.3f} ms/step (eager launches)")
+    info = b.info()
+    reload()
+    b.step(args.warmup)
+    reload()
+    t0 = time.perf_counter()
+    b.step(steps)
+    t = time.perf_counter() - t0
+    ms = 1e3 * t / steps
+    value = upd * steps / t
+    step_gbps = alg / (ms * 1e-3) / 1e9
+    log(f"batch: {ms:.3f} ms/step, {value:.4g} updates/s, {step_gbps:.0f} GB/s algorithmic")
+    # reverse steps of domains 0..31 (state = current fields, seeded gradients)
+    subset = list(range(32))
+    rng = np.random.default_rng(1005)
+    grads = [torch.from_numpy(rng.random(p.shape) - 0.5).to(device="cuda", dtype=g.torch_dtype)
+             if i in subset else None for i, (p, g) in enumerate(zip(probs, grids))]
+    b.set_grads(grads)
+    b.step_adjoint(subset)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.adjoint_steps):
+        b.step_adjoint(subset)
+    ta = (time.perf_counter() - t0) / args.adjoint_steps
+    sub_upd = sum(probs[i].V * probs[i].S for i in subset)
+    log(f"adjoint (32 domains): {1e3 * ta:.3f} ms per reverse step")
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        # bounded sample: one step of the first 12 domains
+        sample = probs[:12]
+        t0 = time.perf_counter()
+        for p in sample:
+            u = np.array(p.u0, copy=True)
+            src = None if p.src is None else oracle.Sources(p.src.voxel, p.src.secretion, p.src.saturation,
+                                                            p.src.uptake)
+            oracle.step(u, p.h, p.D, p.lam, p.dt, src, None, 1)
+        tc = time.perf_counter() - t0
+        su = sum(p.V * p.S for p in sample)
+        cpu = {"value": su / tc, "unit": "voxel-substrate updates/s", "cores": oracle.threads(), "kind": "oracle",
+               "sample": f"1 LOD step of domains 0..11 ({su:.3g} voxel-substrate updates, {tc:.2f} s)"}
+    b.close()
+    line = {
+        "metric": "voxel-substrate updates/s per LOD step (batched domains)",
+        "value": value, "unit": "voxel-substrate updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64 and f32 storage (per domain)",
+        "data": "synthetic (seeded SplitMix64 inputs)",
+        "config": {"workload": "96 uneven domains, axes 24..192, 1..8 substrates, mixed f32/f64, 1% sources",
+                   "domains": len(probs), "f64_domains": n64, "substrate_fields": nsub,
+                   "voxel_substrates": upd, "launches_per_step": info["launches"],
+                   "items_per_step": info["items"], "chunk_elems": info["chunk_elems"]},
+        "roofline": {"bound": "hbm", "achieved": round(step_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(step_gbps / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "scope": "whole step: algorithmic bytes of all launches / step time",
+                     "algorithmic_bytes_per_step": alg},
+        "adjoint": {"domains": 32, "ms_per_reverse_step": round(1e3 * ta, 4),
+                    "voxel_substrates": sub_upd, "updates_per_s": sub_upd / ta},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -164,6 +261,11 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.workload == "batch":
+        run_batch(args)
+        return
+    if args.steps is None:
+        args.steps = 20
     p = workload(args.workload)
     log(f"workload {p.name}: grid {p.nx}x{p.ny}x{p.nz}, S={p.S}, sources "
         f"{0 if p.src is None else len(p.src)}")
