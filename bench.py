@@ -121,6 +121,17 @@ def timed_run(p, dtype, steps, warmup, u_host):
     return g, u, t, stages
 
 
+SWEEP_SOURCES = ["sweep.hip", "seg_solver.hpp", "internal.hpp"]
+
+
+def sweep_source_sha256():
+    """Hash of the sources the sweep kernels are compiled from."""
+    h = hashlib.sha256()
+    for name in SWEEP_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2602_05017_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
 def traffic_record(workload_name, dtype, kernel_stage):
     """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
     taken on the current kernel source; else None."""
@@ -128,9 +139,7 @@ def traffic_record(workload_name, dtype, kernel_stage):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, "paper_2602_05017_amd", "csrc", "sweep.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if rec.get("sweep_src_sha256") != sha:
+    if rec.get("sweep_src_sha256") != sweep_source_sha256():
         return None
     k = rec.get("kernels", {}).get(kernel_stage)
     if not k:
