@@ -52,7 +52,7 @@ def parse():
                     help="batch workload: timed reverse steps of the 32-domain subset")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-storage companion run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=1)
+    ap.add_argument("--cpu-sample-steps", type=int, default=10)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 4 GiB buffer twice (reference for FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()

@@ -201,4 +201,24 @@ struct FastDiv {   // q / d for q * d <= 2^40: (q * m) >> 40
     __device__ __forceinline__ uint32_t div(uint32_t q) const { return (uint32_t)(((uint64_t)q * m) >> 40); }
 };
 
+// XCD-aware tile order.  The dispatcher hands workgroups to the eight XCDs
+// round-robin in launch order (block L goes to XCD L % 8), and each XCD has
+// its own L2.  Giving XCD x the contiguous tile range
+// [x*per + min(x, rem), ...) instead makes neighbouring tiles - which share
+// cache lines and pages when a tile row is narrower than a 128-byte line -
+// run on the same XCD at about the same time.  The map is a bijection of
+// [0, gridDim.x * gridDim.y).
+__device__ __forceinline__ void xcd_tile(uint32_t& bx, uint32_t& by)
+{
+    const uint32_t gx = gridDim.x;
+    const uint32_t nb = gx * gridDim.y;
+    const uint32_t L = blockIdx.y * gx + blockIdx.x;
+    const uint32_t x = L % 8u, q = L / 8u;
+    const uint32_t per = nb / 8u, rem = nb % 8u;
+    const uint32_t t = x * per + (x < rem ? x : rem) + q;
+    by = t / gx;
+    bx = t - by * gx;
+}
+
+
 }  // namespace bfvm

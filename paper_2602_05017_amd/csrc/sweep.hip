@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void k_sweep_line(const T* in, T* out, AxisGeo
 // Block = lpw neighbouring lines x K segments; blockDim = K * lpw.  Lane l of
 // wave w handles line (l % lpw) and segment (w * (64/lpw) + l / lpw), so a
 // wave's load of element k touches 64/lpw runs of lpw consecutive elements.
-// blockIdx.x: line tile, blockIdx.y: outer index.
+// Grid: (line tiles, outer index), visited in the XCD-aware order of xcd_tile.
 
 // Copy the [n][S] coefficient table into LDS for K*M slots in [s][seg][k]
 // layout: slot (i, s) at s*SP + (i/M)*MP + i%M, with MP = M + 1 and SP chosen
@@ -165,6 +165,8 @@ __global__ __launch_bounds__(1024) void k_sweep_seg_strided(const T* in, T* out,
                                                             const C* __restrict__ rr, int lpw, int SP,
                                                             FastDiv divS)
 {
+    uint32_t bx, by;
+    xcd_tile(bx, by);
     extern __shared__ __align__(16) unsigned char smem[];
     const int K = blockDim.x / lpw;
     C* sc = reinterpret_cast<C*>(smem);
@@ -173,7 +175,7 @@ __global__ __launch_bounds__(1024) void k_sweep_seg_strided(const T* in, T* out,
     const int wave = threadIdx.x >> 6;
     const int line = lane % lpw;
     const int seg = wave * (64 / lpw) + lane / lpw;
-    const int64_t p = (int64_t)blockIdx.x * lpw + line;
+    const int64_t p = (int64_t)bx * lpw + line;
     const bool valid = p < g.inner;
     const int64_t pa = valid ? p : g.inner - 1;          // clamped line for padding loads
     const int S = g.S;
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(1024) void k_sweep_seg_strided(const T* in, T* out,
     // XROWS: the x axis run through this kernel; line pa is substrate pa % S of
     // row pa / S, whose elements are S apart inside the row's n*S run
     const int64_t line0 = XROWS ? ((g.p0 + pa) / S) * (g.n * S) + (pa % S)
-                                : (g.o0 + (int64_t)blockIdx.y) * g.outer_stride + g.p0 + pa;
+                                : (g.o0 + (int64_t)by) * g.outer_stride + g.p0 + pa;
     const int64_t base = line0 + i0 * st;
     C v[M];
 #pragma unroll
