@@ -138,7 +138,7 @@ __device__ void batch_tile(const T* in, T* out, const SweepShape& q, int S, int 
     const C* cf = invd + (last >= 0 ? i0 * S + s : s);
 #pragma unroll
     for (int k = 0; k < M; ++k) coef.b[k] = k <= last ? cf[(k <= last ? k : 0) * S] : (C)0;
-    solve_segment<C, M, TR>(v, seg, K, line, lpw, r, coef, sc, true);
+    solve_segment<C, M, TR, false>(v, seg, K, line, lpw, r, coef, sc, true);
     T* op = out + base;
     asm volatile("" : "+v"(op));
 #pragma unroll

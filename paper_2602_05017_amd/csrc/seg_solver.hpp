@@ -17,7 +17,8 @@ namespace bfvm {
 // [segment * nl + line].  They are resolved by one leader thread per line
 // (threads 0..nl-1), which walks the K segments in order with all LDS loads
 // issued ahead of the dependent multiply-add chain and leaves each segment's
-// incoming carry in place of its local value.
+// incoming carry in place of its local value (or, where it fits, by the
+// lane-parallel scan below).
 
 template <typename C>
 __device__ __forceinline__ void carry_scan(C* val, const C* prod, int K, int nl, int line, bool reverse)
@@ -52,6 +53,58 @@ __device__ __forceinline__ void carry_scan(C* val, const C* prod, int K, int nl,
             c = f + g * c;
         }
     }
+}
+
+// Lane-parallel form of the same scan.  When a line's K segments fit one
+// group of KP lanes (KP = the power of two >= K, at most 64) and the block
+// has KP lanes for each of its nl lines, lane q of group l takes segment q
+// (in scan order) of line l and the groups run a log2(KP)-step inclusive
+// scan of the affine maps c -> f + g c through wave shuffles; one more shift
+// turns it into the exclusive carries.  The LDS arrays are then laid out
+// line-major, [line * (KP + 1) + segment], so that both the writers (lanes
+// over lines) and the scan (lanes over segments) touch distinct banks.
+// Kernels choose the scan at compile time (par): the lane-parallel scan pays
+// where few lines have many segments (the LDS row tiles), the leader scan
+// where many lines have few (the strided tiles).
+__host__ __device__ inline int scan_kp(int K, int nl, int threads, bool par)
+{
+    int kp = 1;
+    while (kp < K) kp <<= 1;
+    return (par && kp <= 64 && nl * kp <= threads) ? kp : 0;
+}
+
+// values per carry array: the lane-parallel or the serial layout
+__host__ __device__ inline int scan_slots(int K, int nl, int threads, bool par)
+{
+    const int kp = scan_kp(K, nl, threads, par);
+    return kp ? nl * (kp + 1) : K * nl;
+}
+
+template <typename C>
+__device__ __forceinline__ void carry_scan_par(C* val, const C* prod, int K, int KP, int nl, bool reverse)
+{
+    const int t = threadIdx.x;
+    const int line = t / KP;
+    const int q = t - line * KP;                 // position in scan order
+    const int j = reverse ? K - 1 - q : q;       // segment
+    const bool real = line < nl && q < K;
+    const int at = line * (KP + 1) + j;
+    C f = 0, g = 1;                              // identity map for idle lanes
+    if (real) {
+        f = val[at];
+        g = prod[at];
+    }
+    for (int d = 1; d < KP; d <<= 1) {
+        const C fo = __shfl_up(f, d, KP);
+        const C go = __shfl_up(g, d, KP);
+        if (q >= d) {
+            f = f + g * fo;
+            g = g * go;
+        }
+    }
+    C c = __shfl_up(f, 1, KP);
+    if (q == 0) c = 0;
+    if (real) val[at] = c;
 }
 
 // Ragged tails.  A line of n elements is covered by K segments of M; the
@@ -155,18 +208,20 @@ __device__ __forceinline__ void seg_last(C (&v)[M], C r, const Coef& coef, C X)
 }
 
 // Solve one segment held in v (see the file comment).  sc points to 4 LDS
-// arrays of [K][nl] carry terms indexed [segment * nl + line].  Every thread
-// of the block calls this (it holds barriers); writer = the thread owns a
-// (segment, line) slot.
-template <typename C, int M, bool TR, typename Coef>
+// arrays of scan_slots(K, nl, blockDim.x, PAR) carry terms each.  Every
+// thread of the block calls this (it holds barriers and shuffles); writer =
+// the thread owns a (segment, line) slot.
+template <typename C, int M, bool TR, bool PAR, typename Coef>
 __device__ __forceinline__ void solve_segment(C (&v)[M], int seg, int K, int line, int nl, C r,
                                               const Coef& coef, C* sc, bool writer)
 {
+    const int KP = scan_kp(K, nl, (int)blockDim.x, PAR);
+    const int A = KP ? nl * (KP + 1) : K * nl;
     C* sF = sc;
-    C* sG = sc + K * nl;
-    C* sB = sc + 2 * K * nl;
-    C* sH = sc + 3 * K * nl;
-    const int slot = seg * nl + line;
+    C* sG = sc + A;
+    C* sB = sc + 2 * A;
+    C* sH = sc + 3 * A;
+    const int slot = KP ? line * (KP + 1) + seg : seg * nl + line;
     C f, G;
     seg_forward<C, M, TR>(v, r, coef, f, G);
     if (writer) {
@@ -174,7 +229,8 @@ __device__ __forceinline__ void solve_segment(C (&v)[M], int seg, int K, int lin
         sG[slot] = G;
     }
     __syncthreads();
-    if ((int)threadIdx.x < nl) carry_scan(sF, sG, K, nl, threadIdx.x, false);
+    if (KP) carry_scan_par(sF, sG, K, KP, nl, false);
+    else if ((int)threadIdx.x < nl) carry_scan(sF, sG, K, nl, threadIdx.x, false);
     __syncthreads();
     const C carry = writer ? sF[slot] : (C)0;
     C bw, GB;
@@ -184,7 +240,8 @@ __device__ __forceinline__ void solve_segment(C (&v)[M], int seg, int K, int lin
         sH[slot] = GB;
     }
     __syncthreads();
-    if ((int)threadIdx.x < nl) carry_scan(sB, sH, K, nl, threadIdx.x, true);
+    if (KP) carry_scan_par(sB, sH, K, KP, nl, true);
+    else if ((int)threadIdx.x < nl) carry_scan(sB, sH, K, nl, threadIdx.x, true);
     __syncthreads();
     const C X = writer ? sB[slot] : (C)0;
     seg_last<C, M>(v, r, coef, X);

@@ -170,7 +170,7 @@ __global__ __launch_bounds__(1024) void k_sweep_seg_strided(const T* in, T* out,
     extern __shared__ __align__(16) unsigned char smem[];
     const int K = blockDim.x / lpw;
     C* sc = reinterpret_cast<C*>(smem);
-    C* tab = sc + 4 * K * lpw;
+    C* tab = sc + 4 * scan_slots(K, lpw, (int)blockDim.x, false);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int line = lane % lpw;
@@ -198,10 +198,10 @@ __global__ __launch_bounds__(1024) void k_sweep_seg_strided(const T* in, T* out,
         stage_table<C, M>(tab, invd, (uint32_t)g.n, (uint32_t)(K * M), (uint32_t)S, (uint32_t)SP, divS);
         __syncthreads();
         LdsCoef<C> coef{tab + s * SP + seg * (M + 1), prev};
-        solve_segment<C, M, TR>(v, seg, K, line, lpw, r, coef, sc, true);
+        solve_segment<C, M, TR, false>(v, seg, K, line, lpw, r, coef, sc, true);
     } else {
         GlobalCoef<C> coef{invd + (last >= 0 ? i0 * S + s : s), S, (int)(last < M ? last : M), prev};
-        solve_segment<C, M, TR>(v, seg, K, line, lpw, r, coef, sc, true);
+        solve_segment<C, M, TR, false>(v, seg, K, line, lpw, r, coef, sc, true);
     }
     // An opaque store pointer makes the compiler recompute the M addresses
     // here instead of keeping the load addresses live through the solve.
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(512) void k_sweep_seg_xtile(const T* in, T* out, Ax
         coef.b[k] = k <= last ? cf[(k <= last ? k : 0) * S] : (C)0;
         v[k] = (C)my[(k <= last ? k : last) * S];
     }
-    solve_segment<C, M, TR>(v, j, K, active ? rw * S + s : 0, nl, r, coef, sc, active);
+    solve_segment<C, M, TR, true>(v, j, K, active ? rw * S + s : 0, nl, r, coef, sc, active);
     asm volatile("" : "+v"(my));
     if (cnt == M) {
 #pragma unroll
@@ -356,6 +356,121 @@ __global__ __launch_bounds__(512) void k_sweep_seg_xtile(const T* in, T* out, Ax
     }
 }
 
+// ------------------------------------- kind 4 (x, LDS tile, pipelined rows)
+//
+// The layout and per-thread work of kind 2, in a persistent loop: block b
+// handles row tiles b, b + gridDim.x, ...  A thread's line and segment are
+// the same in every tile, so its M coefficients are loaded once.  The next
+// tile's rows are loaded into registers (P 16-byte chunks per thread) right
+// after the current tile has been written to LDS, so those loads are in
+// flight while the current tile is solved and stored.  Requires the 16-byte
+// conditions of kind 2 and P * blockDim.x chunks >= R * nx * S / (16 / e).
+template <typename T, typename C, int M, bool TR, int P>
+__global__ __launch_bounds__(512) void k_sweep_seg_xpipe(const T* in, T* out, AxisGeom g,
+                                                         const C* __restrict__ invd,
+                                                         const C* __restrict__ rr, int R, int K,
+                                                         int SB, uint32_t tile_bytes,
+                                                         FastDiv divL, FastDiv divMS)
+{
+    // a native 16-byte vector type keeps the prefetch buffer in registers
+    constexpr uint32_t VW = 16 / sizeof(T);
+    typedef T V __attribute__((ext_vector_type(VW)));
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* tile = reinterpret_cast<T*>(smem);
+    const int S = g.S;
+    const int nl = R * S;
+    C* sc = reinterpret_cast<C*>(smem + tile_bytes);
+    const uint32_t L = (uint32_t)(g.n * S);          // row length
+    const uint32_t MS = (uint32_t)(M * S);
+    const uint32_t RS = (uint32_t)(K * SB);           // tile row stride
+    const int64_t ntiles = (g.outer + R - 1) / R;
+
+    const int t = threadIdx.x;
+    const bool active = t < nl * K;
+    const int s = t % S;
+    const int j = (t / S) % K;
+    const int rw = active ? t / (S * K) : 0;
+    const int64_t i0 = (int64_t)j * M;
+    const int64_t last = g.n - 1 - i0;                // slots k > last are padding
+    const C r = rr[s];
+    RegCoef<C, M> coef;
+    coef.prev = (TR && i0 > 0) ? invd[(i0 - 1) * S + s] : (C)0;
+    const C* cf = invd + i0 * S + s;
+#pragma unroll
+    for (int k = 0; k < M; ++k) coef.b[k] = k <= last ? cf[(k <= last ? k : 0) * S] : (C)0;
+
+    // Chunk slots past the tile's end load and store the tile's last chunk:
+    // the duplicate LDS writes carry the same data as the owner's, and the
+    // loop stays branch-free so the prefetch buffer stays in registers.
+    V buf[P];
+    int64_t ti = blockIdx.x;
+    if (ti < ntiles) {
+        const int64_t o0 = ti * R;
+        const uint32_t nch = (uint32_t)min((int64_t)R, g.outer - o0) * L / VW;
+        const V* srcv = reinterpret_cast<const V*>(in + o0 * (int64_t)L);
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            const uint32_t c = t + u * blockDim.x;
+            buf[u] = srcv[c < nch ? c : nch - 1];
+        }
+    }
+    for (; ti < ntiles; ti += gridDim.x) {
+        const int64_t o0 = ti * R;
+        const int nrows = (int)min((int64_t)R, g.outer - o0);
+        const uint32_t nch = (uint32_t)nrows * L / VW;
+        __syncthreads();   // the previous tile's stores have finished reading the LDS tile
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            const uint32_t c0 = t + u * blockDim.x;
+            const uint32_t c = c0 < nch ? c0 : nch - 1;
+            const uint32_t e = c * VW;
+            const uint32_t rw2 = divL.div(e);
+            const uint32_t q = e - rw2 * L;
+            const uint32_t sg = divMS.div(q);
+            *reinterpret_cast<V*>(tile + rw2 * RS + sg * SB + (q - sg * MS)) = buf[u];
+        }
+        __syncthreads();
+        const int64_t tn = ti + gridDim.x;
+        if (tn < ntiles) {   // next tile's rows: in flight during the solve below
+            const int64_t on = tn * R;
+            const uint32_t nchn = (uint32_t)min((int64_t)R, g.outer - on) * L / VW;
+            const V* srcv = reinterpret_cast<const V*>(in + on * (int64_t)L);
+#pragma unroll
+            for (int u = 0; u < P; ++u) {
+                const uint32_t c = t + u * blockDim.x;
+                buf[u] = srcv[c < nchn ? c : nchn - 1];
+            }
+        }
+        const bool valid = active && rw < nrows;
+        const int cnt = valid ? (last >= M ? M : (int)last + 1) : 0;
+        // padding slots read the segment's last real element (row 0 for
+        // threads without a row), so every LDS read is of initialised data
+        const int rws = valid ? rw : 0;
+        T* my = tile + rws * RS + j * SB + s;
+        C v[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) v[k] = (C)my[(k <= last ? k : last) * S];
+        solve_segment<C, M, TR, true>(v, j, K, active ? rw * S + s : 0, nl, r, coef, sc, active);
+        if (cnt == M) {
+#pragma unroll
+            for (int k = 0; k < M; ++k) my[k * S] = (T)v[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < M; ++k)
+                if (k < cnt) my[k * S] = (T)v[k];
+        }
+        __syncthreads();
+        V* dstv = reinterpret_cast<V*>(out + o0 * (int64_t)L);
+        for (uint32_t c = t; c < nch; c += blockDim.x) {
+            const uint32_t e = c * VW;
+            const uint32_t rw2 = divL.div(e);
+            const uint32_t q = e - rw2 * L;
+            const uint32_t sg = divMS.div(q);
+            dstv[c] = *reinterpret_cast<const V*>(tile + rw2 * RS + sg * SB + (q - sg * MS));
+        }
+    }
+}
+
 // ---------------------------------------------------------------- planning
 
 static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -370,13 +485,22 @@ static int xtile_sb(int M, int S, int esize)
     return M * S + pad;
 }
 
-static size_t xtile_lds(int M, int S, int R, int K, int esize, int csize, uint32_t* tile_bytes)
+static size_t xtile_lds(int M, int S, int R, int K, int esize, int csize, int threads, uint32_t* tile_bytes)
 {
     size_t tb = (size_t)R * K * xtile_sb(M, S, esize) * esize;
     tb = (tb + 15) & ~(size_t)15;
     if (tile_bytes) *tile_bytes = (uint32_t)tb;
-    return tb + 4 * (size_t)K * R * S * csize;
+    return tb + 4 * (size_t)scan_slots(K, R * S, threads, true) * csize;
 }
+
+// 16-byte chunks each thread of a kind-4 block prefetches per row tile, and
+// the compiled prefetch depth that covers it (0: none fits)
+static int xpipe_need(const AxisGeom& g, int R, int threads, int es)
+{
+    const int64_t nch = (int64_t)R * g.n * g.S * es / 16;
+    return (int)ceil_div(nch, threads);
+}
+static int xpipe_depth(int need) { return need <= 2 ? 2 : (need <= 4 ? 4 : (need <= 8 ? 8 : 0)); }
 
 static int compute_size(int dtype) { return dtype == DT_F32_FAST ? 4 : 8; }
 
@@ -391,7 +515,7 @@ std::string check_plan(const SweepPlan& p, const AxisGeom& g, int dtype)
         if (g.outer > 65535) return "too many outer blocks for the strided kernel";
         const int64_t K = (int64_t)p.w * 64 / p.lpw;
         if (K * p.m < g.n) return "too few segments for the line length";
-        if (4 * K * p.lpw * cs > kMaxLDS) return "LDS too large";
+        if (4 * (int64_t)scan_slots((int)K, p.lpw, p.w * 64, false) * cs > kMaxLDS) return "LDS too large";
         return "";
     }
     if (p.kind == PLAN_SEG_XROWS) {
@@ -404,8 +528,27 @@ std::string check_plan(const SweepPlan& p, const AxisGeom& g, int dtype)
         const int period = cs == 8 ? 16 : 32;
         const int64_t KM1 = K * (p.m + 1);
         const int64_t SP = KM1 + (((64 / p.lpw - KM1) % period) + period) % period;
-        if ((4 * K * p.lpw + g.S * SP) * cs > kMaxLDS) return "LDS too large (coefficient table)";
+        if ((4 * (int64_t)scan_slots((int)K, p.lpw, p.w * 64, false) + g.S * SP) * cs > kMaxLDS)
+            return "LDS too large (coefficient table)";
         if (K * p.m * g.S >= (1 << 24)) return "line too long";
+        return "";
+    }
+    if (p.kind == PLAN_SEG_XPIPE) {
+        if (g.inner != g.S) return "the pipelined LDS tile kernel only runs the x axis";
+        if (p.m != 8 && p.m != 16) return "m must be 8 or 16 for the pipelined LDS tile kernel";
+        const int64_t K = ceil_div(g.n, p.m);
+        if (p.lpw < 1) return "rows per block must be >= 1";
+        const int64_t threads = K * g.S * p.lpw;
+        if (threads > 512) return "more than 512 threads per block";
+        if ((int64_t)p.w * 64 < threads) return "w too small for the rows";
+        if (p.w > 8) return "w must be <= 8";
+        const int VW = 16 / es;
+        if ((p.m * g.S) % VW || xtile_sb(p.m, g.S, es) % VW || (g.n * g.S) % VW)
+            return "rows must split into 16-byte chunks";
+        const int64_t L = g.n * g.S, tot = L * p.lpw;
+        if (tot >= (1 << 24) || tot * L > (1ll << 40)) return "tile too long";
+        if (!xpipe_depth(xpipe_need(g, p.lpw, p.w * 64, es))) return "row tile too long for the register prefetch";
+        if (xtile_lds(p.m, g.S, p.lpw, (int)K, es, cs, p.w * 64, nullptr) > (size_t)kMaxLDS) return "LDS too large";
         return "";
     }
     if (p.kind == PLAN_SEG_XTILE) {
@@ -419,7 +562,7 @@ std::string check_plan(const SweepPlan& p, const AxisGeom& g, int dtype)
         // FastDiv is exact while (index < 2^24) and index * divisor <= 2^40
         const int64_t L = g.n * g.S, tot = L * p.lpw;
         if (tot >= (1 << 24) || tot * L > (1ll << 40)) return "tile too long";
-        if (xtile_lds(p.m, g.S, p.lpw, (int)K, es, cs, nullptr) > (size_t)kMaxLDS) return "LDS too large";
+        if (xtile_lds(p.m, g.S, p.lpw, (int)K, es, cs, p.w * 64, nullptr) > (size_t)kMaxLDS) return "LDS too large";
         return "";
     }
     return "unknown plan kind";
@@ -430,6 +573,17 @@ SweepPlan default_plan(int axis, const AxisGeom& g, int dtype)
     SweepPlan p;
     const int es = (int)dtype_size(dtype);
     if (axis == 0) {
+        // FP32 storage on long rows: the strided kernel's loads would touch
+        // 16-byte pieces of each row per instruction, so rows go through LDS
+        // with coalesced 16-byte loads, in the pipelined row-tile kernel
+        if (es == 4 && g.n >= 256) {
+            SweepPlan c;
+            c.kind = PLAN_SEG_XPIPE;
+            c.m = 16;
+            c.lpw = 1;
+            c.w = (int)ceil_div(ceil_div(g.n, 16) * g.S, 64);
+            if (check_plan(c, g, dtype).empty()) return c;
+        }
         // preferred: every (row, substrate) as a line of the strided kernel
         {
             const int pm[] = {32, 16, 8, 4};
@@ -489,6 +643,42 @@ SweepPlan default_plan(int axis, const AxisGeom& g, int dtype)
 
 // --------------------------------------------------------------- launching
 
+template <typename T, typename C, bool TR, int M, int P>
+static hipError_t launch_xpipe_p(const SweepPlan& p, const AxisGeom& g, const T* in, T* out, const C* invd,
+                                 const C* r, hipStream_t st)
+{
+    const int K = (int)ceil_div(g.n, M);
+    const int SB = xtile_sb(M, g.S, (int)sizeof(T));
+    uint32_t tile_bytes = 0;
+    const size_t lds = xtile_lds(M, g.S, p.lpw, K, (int)sizeof(T), (int)sizeof(C), p.w * 64, &tile_bytes);
+    const int threads = p.w * 64;
+    auto kern = k_sweep_seg_xpipe<T, C, M, TR, P>;
+    int dev = 0, cus = 0, occ = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, threads, lds) != hipSuccess || occ < 1) occ = 1;
+    const int64_t ntiles = ceil_div(g.outer, p.lpw);
+    const unsigned blocks = (unsigned)std::min<int64_t>(ntiles, (int64_t)cus * occ);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds, st, in, out, g, invd, r, p.lpw, K, SB, tile_bytes,
+                       FastDiv((uint32_t)(g.n * g.S)), FastDiv((uint32_t)(M * g.S)));
+    return hipGetLastError();
+}
+
+template <typename T, typename C, bool TR, int M>
+static hipError_t launch_xpipe(const SweepPlan& p, const AxisGeom& g, const T* in, T* out, const C* invd,
+                               const C* r, hipStream_t st)
+{
+    if constexpr (M == 8 || M == 16) {
+        switch (xpipe_depth(xpipe_need(g, p.lpw, p.w * 64, (int)sizeof(T)))) {
+            case 2: return launch_xpipe_p<T, C, TR, M, 2>(p, g, in, out, invd, r, st);
+            case 4: return launch_xpipe_p<T, C, TR, M, 4>(p, g, in, out, invd, r, st);
+            case 8: return launch_xpipe_p<T, C, TR, M, 8>(p, g, in, out, invd, r, st);
+            default: break;
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
 template <typename T, typename C, bool TR, int M>
 static hipError_t launch_seg(const SweepPlan& p, const AxisGeom& g, const T* in, T* out,
                              const C* invd, const C* r, hipStream_t st)
@@ -503,7 +693,7 @@ static hipError_t launch_seg(const SweepPlan& p, const AxisGeom& g, const T* in,
         const int threads = p.w * 64;
         const int K = threads / p.lpw;
         dim3 grid((unsigned)ceil_div(gg.inner, p.lpw), (unsigned)gg.outer);
-        const size_t scan = 4 * (size_t)K * p.lpw * sizeof(C);
+        const size_t scan = 4 * (size_t)scan_slots(K, p.lpw, threads, false) * sizeof(C);
         // [s][seg][k] table: segment stride M + 1 (odd), substrate stride SP with
         // SP = spw (mod bank period), so the spw segments x S substrates a wave
         // touches at once land in distinct banks
@@ -531,11 +721,13 @@ static hipError_t launch_seg(const SweepPlan& p, const AxisGeom& g, const T* in,
         const int K = (int)ceil_div(g.n, M);
         const int SB = xtile_sb(M, g.S, (int)sizeof(T));
         uint32_t tile_bytes = 0;
-        size_t lds = xtile_lds(M, g.S, p.lpw, K, (int)sizeof(T), (int)sizeof(C), &tile_bytes);
+        size_t lds = xtile_lds(M, g.S, p.lpw, K, (int)sizeof(T), (int)sizeof(C), p.w * 64, &tile_bytes);
         dim3 grid((unsigned)ceil_div(g.outer, p.lpw));
         const int64_t VW = 16 / sizeof(T);
         const bool vec = (M * g.S) % VW == 0 && SB % VW == 0 && (g.n * g.S) % VW == 0 &&
                          (reinterpret_cast<uintptr_t>(in) % 16) == 0 && (reinterpret_cast<uintptr_t>(out) % 16) == 0;
+        // kind 4 needs 16-byte aligned fields; otherwise its plan runs as kind 2
+        if (p.kind == PLAN_SEG_XPIPE && vec) return launch_xpipe<T, C, TR, M>(p, g, in, out, invd, r, st);
         hipLaunchKernelGGL((k_sweep_seg_xtile<T, C, M, TR>), grid, dim3(p.w * 64), lds, st, in, out,
                            g, invd, r, p.lpw, K, SB, tile_bytes, FastDiv((uint32_t)(g.n * g.S)),
                            FastDiv((uint32_t)(M * g.S)), vec);

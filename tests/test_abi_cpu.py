@@ -186,3 +186,34 @@ def test_schedule_selection_and_validation(L):
     small = bf.Grid(64, 64, 64, 1)
     assert small.get_schedule()[0] == 0        # fits the memory-side cache: plain
     small.close()
+
+
+def test_batch_entry_points_validate_before_device_work(L):
+    vp = ctypes.c_void_p
+    out = vp()
+    # NULL out, no domains, NULL arrays
+    assert L.bfvm_batch_create(None, 1, None, None, None) == -1
+    assert L.bfvm_batch_create(ctypes.byref(out), 0, None, None, None) == -1
+    assert not out.value
+    # a grid without params is refused with ESTATE before any allocation
+    st, g = _create(L)
+    assert st == 0
+    grids = (vp * 1)(g.value)
+    fields = (vp * 1)(16)
+    assert L.bfvm_batch_create(ctypes.byref(out), 1, grids, fields, None) == -3
+    assert not out.value
+    nul = (vp * 1)(None)
+    assert L.bfvm_batch_create(ctypes.byref(out), 1, grids, nul, None) == -1
+    L.bfvm_destroy(g)
+    # every batch call rejects a NULL batch
+    i64, i32, dbl = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_double()
+    assert L.bfvm_batch_set_mode(None, 0) == -1
+    assert L.bfvm_batch_set_fields(None, 0, fields) == -1
+    assert L.bfvm_batch_step(None, 1) == -1
+    assert L.bfvm_batch_step_eager(None, 1) == -1
+    assert L.bfvm_batch_step_adjoint(None, 1, None, None, None) == -1
+    assert L.bfvm_batch_autotune(None, None, ctypes.byref(dbl)) == -1
+    assert L.bfvm_batch_get_plan(None, 0, 0, ctypes.byref(i32), ctypes.byref(i32)) == -1
+    assert L.bfvm_batch_info(None, ctypes.byref(i64), ctypes.byref(i32), ctypes.byref(i64)) == -1
+    assert L.bfvm_batch_destroy(None) == 0
+    assert L.bfvm_status_string(-6) == b"feature switched off"

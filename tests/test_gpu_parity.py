@@ -86,6 +86,25 @@ def test_xtile_kernel_plans(m, rows):
     assert emax <= F64_TOL, (m, rows, emax)
 
 
+@pytest.mark.parametrize("m", [8, 16])
+@pytest.mark.parametrize("rows", [1, 2, 3])
+@pytest.mark.parametrize("dtype,tol", [("f64", F64_TOL), ("f32", F32_TOL)])
+def test_xpipe_kernel_plans(m, rows, dtype, tol):
+    # the pipelined row-tile kernel needs rows of whole 16-byte chunks: an x
+    # extent of 48 voxels and 4 substrates; 128 x 101 rows give more row
+    # tiles than the persistent grid holds (256 CUs x at most 12 blocks), so
+    # blocks loop, and 3 rows per tile leave a one-row last tile
+    shape = (48, 128, 101)
+    S = 4
+    p = small_problem(shape, S, seed=330 + m + rows, nsrc=300, ndir=40, nsteps=2)
+    K = math.ceil(shape[0] / m)
+    plans = {0: (4, m, math.ceil(rows * K * S / 64), rows)}
+    ref = oracle_run(p)
+    got = gpu_run(p, dtype=dtype, plans=plans)
+    emax, _ = rel_err(got, ref)
+    assert emax <= tol, (m, rows, emax)
+
+
 @pytest.mark.parametrize("m", [4, 8, 16, 32])
 @pytest.mark.parametrize("lpw", [16, 32, 64])
 def test_xrows_kernel_plans(m, lpw):
