@@ -109,10 +109,11 @@ __device__ __forceinline__ SweepShape sweep_shape(const BDomain& d, int axis)
 }
 
 // One tile of lpw lines (all K = blockDim/lpw segments), as in the strided
-// sweep kernel, with coefficients read from the global table.
+// sweep kernel, with coefficients read from the [n][S] table invd (global,
+// or the block's LDS copy of it).
 template <typename T, typename C, int M, bool TR>
-__device__ void batch_tile(const T* in, T* out, const SweepShape& q, int S, int lpw, int64_t ox, int64_t oy,
-                           const C* __restrict__ invd, const C* __restrict__ rr, C* sc)
+__device__ __forceinline__ void batch_tile(const T* in, T* out, const SweepShape& q, int S, int lpw, int64_t ox,
+                                           int64_t oy, const C* __restrict__ invd, const C* __restrict__ rr, C* sc)
 {
     const int K = blockDim.x / lpw;
     const int lane = threadIdx.x & 63;
@@ -251,11 +252,17 @@ __device__ void batch_sparse_item(const BDomain& d, const BItem& it, double* par
 // ------------------------------------------------------------ grouped mode
 
 // One block per item of one sweep stage (one storage type and M).
+// The axis's [n][S] coefficient table is copied to LDS once per item when it
+// fits (n*S <= kBatchTab), so the tiles read their coefficients from LDS
+// instead of issuing as many global loads as they load field values.
+constexpr int kBatchTab = 2048;
+
 template <typename T, typename C, int M, bool TR>
 __global__ __launch_bounds__(kBatchThreads) void k_group_sweep(const BDomain* __restrict__ doms,
                                                                const BItem* __restrict__ items)
 {
     __shared__ __align__(16) C sc[4 * kBatchThreads];   // carry arrays
+    __shared__ __align__(16) C tab[kBatchTab];
     const BItem it = items[blockIdx.x];
     const BDomain& d = doms[it.dom];
     const SweepShape q = sweep_shape(d, it.axis);
@@ -265,9 +272,19 @@ __global__ __launch_bounds__(kBatchThreads) void k_group_sweep(const BDomain* __
     T* out = static_cast<T*>(d.buf[it.out]);
     const C* invd = static_cast<const C*>(d.invd[it.axis]);
     const C* rr = static_cast<const C*>(d.r[it.axis]);
-    for (int64_t t = it.a0; t < it.a1; ++t) {
-        const int64_t oy = t / tpo, ox = t - oy * tpo;
-        batch_tile<T, C, M, TR>(in, out, q, d.S, lpw, ox, oy, invd, rr, sc);
+    const int64_t nS = q.n * d.S;
+    if (nS <= kBatchTab) {
+        for (int e = threadIdx.x; e < (int)nS; e += blockDim.x) tab[e] = invd[e];
+        __syncthreads();
+        for (int64_t t = it.a0; t < it.a1; ++t) {
+            const int64_t oy = t / tpo, ox = t - oy * tpo;
+            batch_tile<T, C, M, TR>(in, out, q, d.S, lpw, ox, oy, tab, rr, sc);
+        }
+    } else {
+        for (int64_t t = it.a0; t < it.a1; ++t) {
+            const int64_t oy = t / tpo, ox = t - oy * tpo;
+            batch_tile<T, C, M, TR>(in, out, q, d.S, lpw, ox, oy, invd, rr, sc);
+        }
     }
 }
 
