@@ -475,7 +475,20 @@ __global__ __launch_bounds__(512) void k_sweep_seg_xpipe(const T* in, T* out, Ax
 
 static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-static const int kMaxLDS = 64 * 1024;
+// LDS a workgroup may use: the current device's limit (160 KB per workgroup
+// on gfx950), or 64 KB where it cannot be queried (no device).
+static int64_t max_lds()
+{
+    static int64_t cached = -1;
+    if (cached < 0) {
+        int dev = 0, v = 0;
+        cached = 64 * 1024;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > cached)
+            cached = v;
+    }
+    return cached;
+}
 
 // padded segment block (elements of T) for the x tile
 static int xtile_sb(int M, int S, int esize)
@@ -515,7 +528,7 @@ std::string check_plan(const SweepPlan& p, const AxisGeom& g, int dtype)
         if (g.outer > 65535) return "too many outer blocks for the strided kernel";
         const int64_t K = (int64_t)p.w * 64 / p.lpw;
         if (K * p.m < g.n) return "too few segments for the line length";
-        if (4 * (int64_t)scan_slots((int)K, p.lpw, p.w * 64, false) * cs > kMaxLDS) return "LDS too large";
+        if (4 * (int64_t)scan_slots((int)K, p.lpw, p.w * 64, false) * cs > max_lds()) return "LDS too large";
         return "";
     }
     if (p.kind == PLAN_SEG_XROWS) {
@@ -528,7 +541,7 @@ std::string check_plan(const SweepPlan& p, const AxisGeom& g, int dtype)
         const int period = cs == 8 ? 16 : 32;
         const int64_t KM1 = K * (p.m + 1);
         const int64_t SP = KM1 + (((64 / p.lpw - KM1) % period) + period) % period;
-        if ((4 * (int64_t)scan_slots((int)K, p.lpw, p.w * 64, false) + g.S * SP) * cs > kMaxLDS)
+        if ((4 * (int64_t)scan_slots((int)K, p.lpw, p.w * 64, false) + g.S * SP) * cs > max_lds())
             return "LDS too large (coefficient table)";
         if (K * p.m * g.S >= (1 << 24)) return "line too long";
         return "";
@@ -548,7 +561,7 @@ std::string check_plan(const SweepPlan& p, const AxisGeom& g, int dtype)
         const int64_t L = g.n * g.S, tot = L * p.lpw;
         if (tot >= (1 << 24) || tot * L > (1ll << 40)) return "tile too long";
         if (!xpipe_depth(xpipe_need(g, p.lpw, p.w * 64, es))) return "row tile too long for the register prefetch";
-        if (xtile_lds(p.m, g.S, p.lpw, (int)K, es, cs, p.w * 64, nullptr) > (size_t)kMaxLDS) return "LDS too large";
+        if (xtile_lds(p.m, g.S, p.lpw, (int)K, es, cs, p.w * 64, nullptr) > (size_t)max_lds()) return "LDS too large";
         return "";
     }
     if (p.kind == PLAN_SEG_XTILE) {
@@ -562,7 +575,7 @@ std::string check_plan(const SweepPlan& p, const AxisGeom& g, int dtype)
         // FastDiv is exact while (index < 2^24) and index * divisor <= 2^40
         const int64_t L = g.n * g.S, tot = L * p.lpw;
         if (tot >= (1 << 24) || tot * L > (1ll << 40)) return "tile too long";
-        if (xtile_lds(p.m, g.S, p.lpw, (int)K, es, cs, p.w * 64, nullptr) > (size_t)kMaxLDS) return "LDS too large";
+        if (xtile_lds(p.m, g.S, p.lpw, (int)K, es, cs, p.w * 64, nullptr) > (size_t)max_lds()) return "LDS too large";
         return "";
     }
     return "unknown plan kind";
@@ -703,7 +716,7 @@ static hipError_t launch_seg(const SweepPlan& p, const AxisGeom& g, const T* in,
         const int SP = KM1 + (((spw - KM1) % period) + period) % period;
         const size_t tab = (size_t)g.S * SP * sizeof(C);
         const int64_t KMS = (int64_t)K * M * g.S;
-        const bool lds_tab = scan + tab <= (size_t)kMaxLDS && KMS < (1 << 24) && KMS * g.S <= (1ll << 40);
+        const bool lds_tab = scan + tab <= (size_t)max_lds() && KMS < (1 << 24) && KMS * g.S <= (1ll << 40);
         const bool zaxis = g.axis == 2;
         if (xrows)
             hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, true, true, 0>), grid, dim3(threads), scan + tab,
