@@ -168,10 +168,14 @@ int bfvm_get_schedule(bfvm_grid g, int32_t* schedule, int64_t* slab_width);
  * tuner.  kind: 0 one-thread-per-line two-pass kernel, 1 register-segmented
  * kernel with strided loads (y/z), 2 register-segmented kernel staged
  * through LDS (x), 3 the kind-1 kernel with every (row, substrate) of the x
- * axis as one line (x).  m: elements per thread; w: waves per workgroup;
- * lpw: lines per wave (strided kernel) or rows per workgroup (LDS kernel).
- * bfvm_set_plan validates the plan against the grid and returns EINVAL
- * for one that does not fit (too few segments, LDS too large). */
+ * axis as one line (x), 4 the kind-2 layout in a persistent loop that
+ * prefetches the next rows during each solve (x; m 8 or 16, rows of whole
+ * 16-byte chunks; runs as kind 2 on a field that is not 16-byte aligned).
+ * m: elements per thread; w: waves per workgroup; lpw: lines per wave
+ * (strided kernels) or rows per workgroup (LDS kernels).  bfvm_set_plan
+ * validates the plan against the grid and the device's LDS per workgroup
+ * and returns EINVAL for one that does not fit (too few segments, LDS too
+ * large, rows that do not split into 16-byte chunks). */
 int bfvm_get_plan(bfvm_grid g, int32_t axis, int32_t* kind, int32_t* m, int32_t* w, int32_t* lpw);
 int bfvm_set_plan(bfvm_grid g, int32_t axis, int32_t kind, int32_t m, int32_t w, int32_t lpw);
 

@@ -141,6 +141,17 @@ def test_set_plan_rejects_plans_that_do_not_fit(L):
     assert L.bfvm_set_plan(g, 0, 2, 4, 1, 1) == -1       # too few waves for 25 x 4 threads
     assert L.bfvm_set_plan(g, 0, 9, 4, 1, 1) == -1
     assert L.bfvm_set_plan(g, 2, 0, 0, 0, 0) == 0        # the line kernel always fits
+    assert L.bfvm_set_plan(g, 1, 4, 16, 4, 1) == -1      # pipelined row tiles are x only
+    assert L.bfvm_set_plan(g, 0, 4, 4, 4, 1) == -1       # m 8 or 16 only
+    assert L.bfvm_set_plan(g, 0, 4, 16, 1, 1) == 0       # 7 segments x 4 substrates: one wave
+    assert L.bfvm_set_plan(g, 0, 4, 16, 1, 2) == 0       # two rows: 56 threads, 8 chunks each
+    assert L.bfvm_set_plan(g, 0, 4, 16, 1, 3) == -1      # three rows need 84 threads
+    assert L.bfvm_set_plan(g, 0, 4, 16, 9, 1) == -1      # more than 8 waves
+    assert L.bfvm_set_plan(g, 0, 4, 8, 1, 4) == -1       # 13 segments x 4 substrates x 4 rows > 1 wave
+    L.bfvm_destroy(g)
+    st, g = _create(L, 101, 8, 8, 1)                     # 101 doubles per row: not whole 16-byte chunks
+    assert L.bfvm_set_plan(g, 0, 4, 16, 1, 1) == -1
+    assert L.bfvm_set_plan(g, 0, 2, 16, 1, 1) == 0       # the unpipelined LDS kernel takes any row
     L.bfvm_destroy(g)
 
 
