@@ -49,7 +49,7 @@ extern "C" {
 #define BFVM_ESTATE  (-3)   /* call out of order (e.g. step before set_params) */
 #define BFVM_EDEVICE (-4)   /* HIP runtime error; bfvm_last_error() has hipGetErrorString text */
 #define BFVM_ENOMEM  (-5)   /* host or device allocation failed */
-#define BFVM_EOFF    (-6)   /* the requested feature is switched off in this build */
+#define BFVM_EOFF    (-6)   /* the requested feature is switched off in this library version */
 
 /* ---- storage / arithmetic types ---------------------------------------- */
 #define BFVM_F64       0    /* double storage, double arithmetic, double coefficients */
