@@ -195,7 +195,8 @@ int bfvm_set_plan(bfvm_grid g, int32_t axis, int32_t kind, int32_t m, int32_t w,
  *
  * The member grids are borrowed: they must stay alive, and their params,
  * sources and Dirichlet lists must not change, while the batch exists.
- * Line lengths up to 256 are supported.  The batch's calls are not
+ * Line lengths up to 256 are supported, with line length x substrates at
+ * most 2048 on every axis (e.g. 256 voxels x 8 substrates).  The batch's calls are not
  * thread-safe; calls on one batch from several threads must be serialised.
  */
 typedef struct bfvm_batch_s* bfvm_batch;
@@ -206,8 +207,9 @@ typedef struct bfvm_batch_s* bfvm_batch;
 /* grids[ndomains] (each with set_params done) and fields[ndomains] (device
  * pointers, each holding its grid's field).  stream = hipStream_t; NULL makes
  * the batch create its own non-blocking stream (graphs cannot capture the
- * null stream).  Errors: EINVAL (sizes, NULLs, line longer than 256),
- * ESTATE (a grid without params), ENOMEM, EDEVICE. */
+ * null stream).  Errors: EINVAL (sizes, NULLs, line longer than 256 or
+ * line x substrates above 2048), ESTATE (a grid without params), ENOMEM,
+ * EDEVICE. */
 int bfvm_batch_create(bfvm_batch* out, int32_t ndomains, const bfvm_grid* grids, void* const* fields,
                       void* stream);
 int bfvm_batch_destroy(bfvm_batch b);

@@ -50,6 +50,7 @@ enum StageType : int32_t {
 };
 
 constexpr int kBatchThreads = 512;
+constexpr int kBatchTab = 2048;   // line length x substrates, per axis
 // elements per thread M in {4, 8} and at most 512/16 = 32 segments per line
 constexpr int64_t kMaxBatchLine = 256;
 constexpr int kNumBuf = 5;   // 0 field, 1 gradient, 2..4 adjoint workspace
@@ -110,12 +111,18 @@ __device__ __forceinline__ SweepShape sweep_shape(const BDomain& d, int axis)
 
 // One tile of lpw lines (all K = blockDim/lpw segments), as in the strided
 // sweep kernel, with coefficients read from the [n][S] table invd (global,
-// or the block's LDS copy of it).
-template <typename T, typename C, int M, bool TR>
-__device__ __forceinline__ void batch_tile(const T* in, T* out, const SweepShape& q, int S, int lpw, int64_t ox,
-                                           int64_t oy, const C* __restrict__ invd, const C* __restrict__ rr, C* sc)
+// or the block's LDS copy of it).  Split into the thread's tile geometry,
+// the load of its M values (in storage precision) and the solve + store, so
+// that a loop over tiles can load the next tile while it solves this one.
+struct TileSpot {
+    int64_t base;    // element index of the thread's first slot
+    int64_t last;    // n - 1 - i0: slots k > last are padding
+    int cnt;         // slots to store
+    int s;           // substrate
+};
+
+__device__ __forceinline__ TileSpot tile_spot(const SweepShape& q, int S, int lpw, int M, int64_t ox, int64_t oy)
 {
-    const int K = blockDim.x / lpw;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int line = lane % lpw;
@@ -123,28 +130,59 @@ __device__ __forceinline__ void batch_tile(const T* in, T* out, const SweepShape
     const int64_t p = ox * lpw + line;
     const bool valid = p < q.inner;
     const int64_t pa = valid ? p : q.inner - 1;
-    const int s = (int)(pa % S);
+    TileSpot t;
+    t.s = (int)(pa % S);
     const int64_t i0 = (int64_t)seg * M;
-    const int64_t last = q.n - 1 - i0;
-    const int cnt = !valid || last < 0 ? 0 : (last >= M ? M : (int)last + 1);
-    const int64_t st = q.stride;
+    t.last = q.n - 1 - i0;
+    t.cnt = !valid || t.last < 0 ? 0 : (t.last >= M ? M : (int)t.last + 1);
     const int64_t line0 = q.xrows ? (pa / S) * q.row_len + (pa % S) : oy * q.outer_stride + pa;
-    const int64_t base = line0 + i0 * st;
+    t.base = line0 + i0 * q.stride;
+    return t;
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void tile_load(const T* in, const TileSpot& t, int64_t st, T (&raw)[M])
+{
+#pragma unroll
+    for (int k = 0; k < M; ++k) raw[k] = in[t.base + (k <= t.last ? k : t.last) * st];
+}
+
+template <typename T, typename C, int M, bool TR>
+__device__ __forceinline__ void tile_solve_store(T* out, const TileSpot& t, int64_t st, const T (&raw)[M], int S,
+                                                 int lpw, const C* __restrict__ invd, const C* __restrict__ rr,
+                                                 C* sc)
+{
+    const int K = blockDim.x / lpw;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int line = lane % lpw;
+    const int seg = wave * (64 / lpw) + lane / lpw;
+    const int64_t i0 = (int64_t)seg * M;
     C v[M];
 #pragma unroll
-    for (int k = 0; k < M; ++k) v[k] = (C)in[base + (k <= last ? k : last) * st];
-    const C r = rr[s];
+    for (int k = 0; k < M; ++k) v[k] = (C)raw[k];
+    const C r = rr[t.s];
     RegCoef<C, M> coef;
-    coef.prev = (TR && i0 > 0 && last >= 0) ? invd[(i0 - 1) * S + s] : (C)0;
-    const C* cf = invd + (last >= 0 ? i0 * S + s : s);
+    coef.prev = (TR && i0 > 0 && t.last >= 0) ? invd[(i0 - 1) * S + t.s] : (C)0;
+    const C* cf = invd + (t.last >= 0 ? i0 * S + t.s : t.s);
 #pragma unroll
-    for (int k = 0; k < M; ++k) coef.b[k] = k <= last ? cf[(k <= last ? k : 0) * S] : (C)0;
+    for (int k = 0; k < M; ++k) coef.b[k] = k <= t.last ? cf[(k <= t.last ? k : 0) * S] : (C)0;
     solve_segment<C, M, TR, false>(v, seg, K, line, lpw, r, coef, sc, true);
-    T* op = out + base;
+    T* op = out + t.base;
     asm volatile("" : "+v"(op));
 #pragma unroll
     for (int k = 0; k < M; ++k)
-        if (k < cnt) op[k * st] = (T)v[k];
+        if (k < t.cnt) op[k * st] = (T)v[k];
+}
+
+template <typename T, typename C, int M, bool TR>
+__device__ __forceinline__ void batch_tile(const T* in, T* out, const SweepShape& q, int S, int lpw, int64_t ox,
+                                           int64_t oy, const C* __restrict__ invd, const C* __restrict__ rr, C* sc)
+{
+    const TileSpot t = tile_spot(q, S, lpw, M, ox, oy);
+    T raw[M];
+    tile_load<T, M>(in, t, q.stride, raw);
+    tile_solve_store<T, C, M, TR>(out, t, q.stride, raw, S, lpw, invd, rr, sc);
 }
 
 template <typename T, typename C, bool TR>
@@ -252,14 +290,14 @@ __device__ void batch_sparse_item(const BDomain& d, const BItem& it, double* par
 // ------------------------------------------------------------ grouped mode
 
 // One block per item of one sweep stage (one storage type and M).
-// The axis's [n][S] coefficient table is copied to LDS once per item when it
-// fits (n*S <= kBatchTab), so the tiles read their coefficients from LDS
-// instead of issuing as many global loads as they load field values.
-constexpr int kBatchTab = 2048;
+// The axis's [n][S] coefficient table (n*S <= kBatchTab) is copied to LDS
+// once per item, so the tiles read their coefficients from LDS instead of
+// issuing as many global loads as they load field values.
 
+// M <= 8: at most 128 VGPRs, so that two 512-thread blocks fit per CU
 template <typename T, typename C, int M, bool TR>
-__global__ __launch_bounds__(kBatchThreads) void k_group_sweep(const BDomain* __restrict__ doms,
-                                                               const BItem* __restrict__ items)
+__global__ __launch_bounds__(kBatchThreads, M <= 8 ? 4 : 2) void k_group_sweep(const BDomain* __restrict__ doms,
+                                                                               const BItem* __restrict__ items)
 {
     __shared__ __align__(16) C sc[4 * kBatchThreads];   // carry arrays
     __shared__ __align__(16) C tab[kBatchTab];
@@ -272,19 +310,12 @@ __global__ __launch_bounds__(kBatchThreads) void k_group_sweep(const BDomain* __
     T* out = static_cast<T*>(d.buf[it.out]);
     const C* invd = static_cast<const C*>(d.invd[it.axis]);
     const C* rr = static_cast<const C*>(d.r[it.axis]);
-    const int64_t nS = q.n * d.S;
-    if (nS <= kBatchTab) {
-        for (int e = threadIdx.x; e < (int)nS; e += blockDim.x) tab[e] = invd[e];
-        __syncthreads();
-        for (int64_t t = it.a0; t < it.a1; ++t) {
-            const int64_t oy = t / tpo, ox = t - oy * tpo;
-            batch_tile<T, C, M, TR>(in, out, q, d.S, lpw, ox, oy, tab, rr, sc);
-        }
-    } else {
-        for (int64_t t = it.a0; t < it.a1; ++t) {
-            const int64_t oy = t / tpo, ox = t - oy * tpo;
-            batch_tile<T, C, M, TR>(in, out, q, d.S, lpw, ox, oy, invd, rr, sc);
-        }
+    const int nS = (int)(q.n * d.S);   // <= kBatchTab (checked when the batch is created)
+    for (int e = threadIdx.x; e < nS; e += blockDim.x) tab[e] = invd[e];
+    __syncthreads();
+    for (int64_t t = it.a0; t < it.a1; ++t) {
+        const int64_t oy = t / tpo, ox = t - oy * tpo;
+        batch_tile<T, C, M, TR>(in, out, q, d.S, lpw, ox, oy, tab, rr, sc);
     }
 }
 
@@ -812,6 +843,8 @@ int bfvm_batch_create(bfvm_batch* out, int32_t ndomains, const bfvm_grid* grids,
         for (int a = 0; a < 3; ++a) {
             const int64_t n = a == 0 ? grids[i]->nx : (a == 1 ? grids[i]->ny : grids[i]->nz);
             if (n > kMaxBatchLine) return bfail(BFVM_EINVAL, "batched domains support line lengths up to 256");
+            if (n * grids[i]->S > kBatchTab)
+                return bfail(BFVM_EINVAL, "batched domains support line length x substrates up to 2048");
         }
     }
     bfvm_batch b = new (std::nothrow) bfvm_batch_s();
