@@ -610,15 +610,22 @@ int bfvm_step_adjoint(bfvm_grid g, const void* field_in, void* grad, double* gra
     if (!g->red_out) HIP_TRY(hipMalloc((void**)&g->red_out, sizeof(double) * 2 * S * 3), "hipMalloc red_out");
     hipStream_t st = g->stream;
     int rc;
-    // forward recomputation: work[a] = output of sweep a (before the following Dirichlet)
+    // forward recomputation: work[a] = output of sweep a (before the following
+    // Dirichlet overwrite).  Without Dirichlet entries sweep a reads work[a-1]
+    // directly; with them it runs on an overwritten copy, so that work[a-1]
+    // keeps the sweep output the reduction needs.
     HIP_TRY(hipMemcpyAsync(g->work[0], field_in, bytes, hipMemcpyDeviceToDevice, st), "copy");
     if ((rc = run_source(g, g->work[0]))) return rc;
     if ((rc = run_dirichlet(g, g->work[0]))) return rc;
     if ((rc = run_sweep(g, 0, g->work[0], g->work[0], false))) return rc;
     for (int a = 1; a < 3; ++a) {
-        HIP_TRY(hipMemcpyAsync(g->work[a], g->work[a - 1], bytes, hipMemcpyDeviceToDevice, st), "copy");
-        if ((rc = run_dirichlet(g, g->work[a]))) return rc;
-        if ((rc = run_sweep(g, a, g->work[a], g->work[a], false))) return rc;
+        if (g->ndir > 0) {
+            HIP_TRY(hipMemcpyAsync(g->work[a], g->work[a - 1], bytes, hipMemcpyDeviceToDevice, st), "copy");
+            if ((rc = run_dirichlet(g, g->work[a]))) return rc;
+            if ((rc = run_sweep(g, a, g->work[a], g->work[a], false))) return rc;
+        } else if ((rc = run_sweep(g, a, g->work[a - 1], g->work[a], false))) {
+            return rc;
+        }
     }
     // reverse: Dir^T, Z^T, Dir^T, Y^T, Dir^T, X^T, Dir^T, Src^T
     for (int a = 2; a >= 0; --a) {
