@@ -142,18 +142,32 @@ __global__ __launch_bounds__(256) void k_adj_partials(const T* __restrict__ y, c
     }
 }
 
-__global__ void k_adj_final(const double* __restrict__ partials, int64_t nb, int S,
-                            double* __restrict__ out)
+// Second stage: block s sums substrate s's nb partial pairs, each thread a
+// fixed strided subset, then a fixed-order tree: deterministic.
+__global__ __launch_bounds__(256) void k_adj_final(const double* __restrict__ partials, int64_t nb, int S,
+                                                   double* __restrict__ out)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S) return;
+    __shared__ double s0[256], s1[256];
+    const int s = blockIdx.x;
     double a0 = 0.0, a1 = 0.0;
-    for (int64_t b = 0; b < nb; ++b) {
+    for (int64_t b = threadIdx.x; b < nb; b += 256) {
         a0 += partials[((int64_t)s * nb + b) * 2 + 0];
         a1 += partials[((int64_t)s * nb + b) * 2 + 1];
     }
-    out[s * 2 + 0] = a0;
-    out[s * 2 + 1] = a1;
+    s0[threadIdx.x] = a0;
+    s1[threadIdx.x] = a1;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s0[threadIdx.x] += s0[threadIdx.x + w];
+            s1[threadIdx.x] += s1[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[s * 2 + 0] = s0[0];
+        out[s * 2 + 1] = s1[0];
+    }
 }
 
 int64_t adjoint_reduce_blocks(int64_t nvox)
@@ -176,7 +190,7 @@ hipError_t launch_adjoint_reduce(int dtype, const void* y, const void* x, const 
                                          vstride, g.n, S, partials));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_adj_final, dim3(blocks_for(S, 64)), dim3(64), 0, st, partials, nb, S, out);
+    hipLaunchKernelGGL(k_adj_final, dim3((unsigned)S), dim3(256), 0, st, partials, nb, S, out);
     return hipGetLastError();
 }
 
