@@ -166,3 +166,56 @@ def test_persistent_mode_is_refused():
     with pytest.raises(bf.BfvmError) as ei:
         bf.Batch(grids, fields, mode="persistent")
     assert ei.value.code == "EOFF"
+
+
+def test_full_batch_workload_autotuned_100_steps():
+    # the benchmark's batch: 96 domains, autotuned plans, 100 graph replays;
+    # every domain against its own single-grid GPU run, and the two smallest
+    # domains of each storage type against the oracle
+    import torch
+    import paper_2602_05017_amd as bf
+    probs = workloads.batch_config()
+    assert len(probs) == 96 and probs[0].nsteps == 100
+    grids, fields = _setup(probs)
+    b = bf.Batch(grids, fields)
+    b.autotune(None)
+    for p, g, f in zip(probs, grids, fields):
+        f.copy_(upload(p, g))
+    torch.cuda.synchronize()
+    b.step(100)
+    got = [g.read_field(f) for g, f in zip(grids, fields)]
+    b.close()
+    worst = {}
+    for p, out in zip(probs, got):
+        single = make_grid(p, p.dtype)
+        u = upload(p, single)
+        single.step(u, 100)
+        torch.cuda.synchronize()
+        ref = single.read_field(u)
+        single.close()
+        e = rel_err(out, ref)[0]
+        worst[p.dtype] = max(worst.get(p.dtype, 0.0), e)
+        assert e <= TOL[p.dtype], (p.name, e)
+    print(f"96 domains vs single-grid runs, 100 steps: worst e_max {worst}")
+    by_size = sorted(range(96), key=lambda k: probs[k].V * probs[k].S)
+    sample = [i for i in by_size if probs[i].dtype == "f64"][:2] + [i for i in by_size if probs[i].dtype == "f32"][:2]
+    for i in sample:
+        p = probs[i]
+        u = np.array(p.u0, copy=True)
+        src, dr = oracle_lists(p)
+        oracle.step(u, p.h, p.D, p.lam, p.dt, src, dr, 100)
+        e = rel_err(got[i], u)[0]
+        print(f"{p.name} {p.dtype} {p.nx}x{p.ny}x{p.nz}x{p.S} vs oracle, 100 steps: e_max {e:.3e}")
+        assert e <= TOL[p.dtype]
+
+
+def test_batch_rejects_tables_too_large_for_lds():
+    import paper_2602_05017_amd as bf
+    g = bf.Grid(256, 24, 24, 9, (10.0, 10.0, 10.0), dtype="f64")   # 256 x 9 > 2048 on x
+    g.set_params(np.full(9, 1e3), np.full(9, 0.1), 0.01)
+    import torch
+    u = torch.zeros((24, 24, 256, 9), dtype=torch.float64, device="cuda")
+    with pytest.raises(bf.BfvmError) as ei:
+        bf.Batch([g], [u])
+    assert ei.value.code == "EINVAL"
+    g.close()

@@ -222,10 +222,16 @@ def test_duplicate_sources_and_dirichlet_entries():
     assert flat[3, 0] == val[1, 0] and flat[3, 1] == val[0, 1]
 
 
-def test_cells_full_size_two_steps():
-    p = workloads.config(2, nsteps=2)     # 256^3 x 8, 1e5 sources, 64 Dirichlet voxels
+def test_cells_full_workload_100_steps():
+    # the 256^3 x 8 workload exactly: 1e5 sources, 64 Dirichlet voxels, 100 steps
+    p = workloads.config(2)
+    assert p.nsteps == 100
     ref = oracle_run(p)
     got = gpu_run(p)
     emax, e2 = rel_err(got, ref)
-    print(f"cells 256^3x8 f64 2 steps: e_max={emax:.3e} e_2={e2:.3e}")
+    print(f"cells 256^3x8 f64 100 steps: e_max={emax:.3e} e_2={e2:.3e}")
     assert emax <= F64_TOL
+    # every active Dirichlet entry holds its value exactly after the last step
+    flat = got.reshape(-1, p.S)
+    act = p.dr.active.astype(bool)
+    assert np.array_equal(flat[p.dr.voxel[act[:, 0]], 0], p.dr.value[act[:, 0], 0])
