@@ -114,9 +114,12 @@ __device__ __forceinline__ SweepShape sweep_shape(const BDomain& d, int axis)
 // or the block's LDS copy of it).  Split into the thread's tile geometry,
 // the load of its M values (in storage precision) and the solve + store, so
 // that a loop over tiles can load the next tile while it solves this one.
+// Element indices are signed 32-bit (a batched domain has < 2^31 elements):
+// a padding slot's index base + last * st, with last < 0, is then the line's
+// last element, computed without leaving the domain.
 struct TileSpot {
-    int64_t base;    // element index of the thread's first slot
-    int64_t last;    // n - 1 - i0: slots k > last are padding
+    int base;        // element index of the thread's first slot
+    int last;        // n - 1 - i0: slots k > last are padding
     int cnt;         // slots to store
     int s;           // substrate
 };
@@ -127,28 +130,30 @@ __device__ __forceinline__ TileSpot tile_spot(const SweepShape& q, int S, int lp
     const int wave = threadIdx.x >> 6;
     const int line = lane % lpw;
     const int seg = wave * (64 / lpw) + lane / lpw;
-    const int64_t p = ox * lpw + line;
-    const bool valid = p < q.inner;
-    const int64_t pa = valid ? p : q.inner - 1;
+    const uint32_t inner = (uint32_t)q.inner;
+    const uint32_t p = (uint32_t)ox * lpw + line;
+    const bool valid = p < inner;
+    const uint32_t pa = valid ? p : inner - 1;
     TileSpot t;
-    t.s = (int)(pa % S);
-    const int64_t i0 = (int64_t)seg * M;
-    t.last = q.n - 1 - i0;
-    t.cnt = !valid || t.last < 0 ? 0 : (t.last >= M ? M : (int)t.last + 1);
-    const int64_t line0 = q.xrows ? (pa / S) * q.row_len + (pa % S) : oy * q.outer_stride + pa;
-    t.base = line0 + i0 * q.stride;
+    t.s = (int)(pa % (uint32_t)S);
+    const int i0 = seg * M;
+    t.last = (int)q.n - 1 - i0;
+    t.cnt = !valid || t.last < 0 ? 0 : (t.last >= M ? M : t.last + 1);
+    const int line0 = q.xrows ? (int)((pa / S) * (uint32_t)q.row_len) + t.s
+                              : (int)oy * (int)q.outer_stride + (int)pa;
+    t.base = line0 + i0 * (int)q.stride;
     return t;
 }
 
 template <typename T, int M>
-__device__ __forceinline__ void tile_load(const T* in, const TileSpot& t, int64_t st, T (&raw)[M])
+__device__ __forceinline__ void tile_load(const T* in, const TileSpot& t, int st, T (&raw)[M])
 {
 #pragma unroll
     for (int k = 0; k < M; ++k) raw[k] = in[t.base + (k <= t.last ? k : t.last) * st];
 }
 
 template <typename T, typename C, int M, bool TR>
-__device__ __forceinline__ void tile_solve_store(T* out, const TileSpot& t, int64_t st, const T (&raw)[M], int S,
+__device__ __forceinline__ void tile_solve_store(T* out, const TileSpot& t, int st, const T (&raw)[M], int S,
                                                  int lpw, const C* __restrict__ invd, const C* __restrict__ rr,
                                                  C* sc)
 {
@@ -157,7 +162,7 @@ __device__ __forceinline__ void tile_solve_store(T* out, const TileSpot& t, int6
     const int wave = threadIdx.x >> 6;
     const int line = lane % lpw;
     const int seg = wave * (64 / lpw) + lane / lpw;
-    const int64_t i0 = (int64_t)seg * M;
+    const int i0 = seg * M;
     C v[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) v[k] = (C)raw[k];
@@ -181,8 +186,8 @@ __device__ __forceinline__ void batch_tile(const T* in, T* out, const SweepShape
 {
     const TileSpot t = tile_spot(q, S, lpw, M, ox, oy);
     T raw[M];
-    tile_load<T, M>(in, t, q.stride, raw);
-    tile_solve_store<T, C, M, TR>(out, t, q.stride, raw, S, lpw, invd, rr, sc);
+    tile_load<T, M>(in, t, (int)q.stride, raw);
+    tile_solve_store<T, C, M, TR>(out, t, (int)q.stride, raw, S, lpw, invd, rr, sc);
 }
 
 template <typename T, typename C, bool TR>
@@ -846,6 +851,8 @@ int bfvm_batch_create(bfvm_batch* out, int32_t ndomains, const bfvm_grid* grids,
             if (n * grids[i]->S > kBatchTab)
                 return bfail(BFVM_EINVAL, "batched domains support line length x substrates up to 2048");
         }
+        // (implied by the two limits above: the kernels use 32-bit element offsets)
+        if (grids[i]->nelem() >= (1ll << 31)) return bfail(BFVM_EINVAL, "batched domain too large");
     }
     bfvm_batch b = new (std::nothrow) bfvm_batch_s();
     if (!b) return bfail(BFVM_ENOMEM, "host allocation failed");
