@@ -132,6 +132,24 @@ int bfvm_sweep(bfvm_grid g, void* field, int32_t axis);
 int bfvm_step_adjoint(bfvm_grid g, const void* field_in, void* grad,
                       double* grad_D, double* grad_lambda);
 
+/* ---- device-side field set-up ----------------------------------------- */
+/* Fill a device field of this grid with seeded uniform values in [lo, hi):
+ * element i (layout index) = lo + (hi - lo) * U_i, where U_i = (key_i >> 11)
+ * * 2^-53, key_i = mix(k ^ i), k = mix(seed ^ (stream << 56)) and mix is the
+ * SplitMix64 finaliser (Steele, Lea and Flood, OOPSLA 2014).  FP32 fields
+ * get the double value rounded to nearest.  Enqueued on the grid's stream;
+ * nothing is copied through host memory (grids beyond host RAM).
+ * Errors: EINVAL (NULL field, non-finite or reversed bounds). */
+int bfvm_fill_uniform(bfvm_grid g, void* field, uint64_t seed, uint32_t stream, double lo, double hi);
+
+/* The Gaussian initial profile of the end-to-end run (Sec. 5.3), plus seeded
+ * noise: element (z, y, x, s) = peak * exp(-d^2 / (2 sigma^2)) + noise * U_i,
+ * d = distance of the voxel centre (x + 1/2, y + 1/2, z + 1/2) from (cx, cy,
+ * cz), in voxel units; U_i as in bfvm_fill_uniform.  Enqueued on the grid's
+ * stream.  Errors: EINVAL (NULL field, sigma <= 0, non-finite values). */
+int bfvm_fill_gaussian(bfvm_grid g, void* field, double cx, double cy, double cz, double sigma, double peak,
+                       double noise, uint64_t seed, uint32_t stream);
+
 /* Copy a device field of this grid to host memory (host_dst holds
  * nx*ny*nz*nsub elements of the grid's storage type).  Synchronising.
  * Errors: EINVAL, EDEVICE. */

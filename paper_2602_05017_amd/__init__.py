@@ -30,6 +30,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ERANGE", -3: "ESTATE", -4: "EDEVICE", -5: 
 EXPORTS = [
     "bfvm_create", "bfvm_destroy", "bfvm_set_stream", "bfvm_set_params", "bfvm_set_sources",
     "bfvm_set_dirichlet", "bfvm_step", "bfvm_sweep", "bfvm_step_adjoint", "bfvm_read_field",
+    "bfvm_fill_uniform", "bfvm_fill_gaussian",
     "bfvm_timing_enable", "bfvm_timing_read", "bfvm_timing_reset", "bfvm_timing_elements",
     "bfvm_set_schedule", "bfvm_get_schedule", "bfvm_get_plan", "bfvm_set_plan",
     "bfvm_batch_create", "bfvm_batch_destroy", "bfvm_batch_set_mode", "bfvm_batch_set_fields", "bfvm_batch_step",
@@ -230,6 +231,24 @@ class Grid:
         self._sync_stream()
         _check(lib().bfvm_step_adjoint(self._handle, pin, pg, _ptr(gD), _ptr(gL)), "bfvm_step_adjoint")
         return gD, gL
+
+    def fill_uniform(self, field, seed: int, stream: int = 0, lo: float = 0.0, hi: float = 1.0):
+        """Seeded uniform values in [lo, hi) written on the device (SplitMix64 counter stream)."""
+        p = self._field_ptr(field)
+        self._sync_stream()
+        _check(lib().bfvm_fill_uniform(self._handle, p, ctypes.c_uint64(seed), ctypes.c_uint32(stream),
+                                       ctypes.c_double(lo), ctypes.c_double(hi)), "bfvm_fill_uniform")
+
+    def fill_gaussian(self, field, center, sigma: float, peak: float = 1.0, noise: float = 0.0, seed: int = 0,
+                      stream: int = 0):
+        """Gaussian profile (voxel-centre coordinates) plus noise * U, written on the device.
+        center = (cx, cy, cz) in voxel units."""
+        p = self._field_ptr(field)
+        self._sync_stream()
+        cx, cy, cz = (float(c) for c in center)
+        _check(lib().bfvm_fill_gaussian(self._handle, p, _dbl(cx), _dbl(cy), _dbl(cz), _dbl(sigma), _dbl(peak),
+                                        _dbl(noise), ctypes.c_uint64(seed), ctypes.c_uint32(stream)),
+               "bfvm_fill_gaussian")
 
     def read_field(self, field) -> np.ndarray:
         p = self._field_ptr(field)

@@ -84,6 +84,25 @@ void thomas_constants(int64_t n, double r, double beta, int S, int s, double* in
     }
 }
 
+// Head length H of the exact compressed form of an axis's [n][S] table: the
+// smallest H such that, for every substrate, slots H .. n-2 all equal slot H
+// bit for bit; -1 when there is none short enough to pay (H + 2 >= n or
+// H > kCompHeadMax).
+const int kCompHeadMax = 512;
+
+int comp_head(const std::vector<double>& invd, int64_t n, int S)
+{
+    if (n < 4) return -1;
+    int H = 0;
+    for (int s = 0; s < S; ++s) {
+        int64_t h = n - 2;   // walk back from the last interior slot while equal to it
+        const double c = invd[(n - 2) * S + s];
+        while (h > 0 && invd[(h - 1) * S + s] == c) --h;
+        H = std::max<int>(H, (int)h);
+    }
+    return (H + 2 < n && H <= kCompHeadMax) ? H : -1;
+}
+
 int merge_sources(bfvm_grid g)
 {
     const int S = g->S;
@@ -188,9 +207,11 @@ int run_sweep_geo(bfvm_grid g, int axis, const AxisGeom& geo, const void* in, vo
     const bool f32c = g->dtype == BFVM_F32_FAST;
     const void* invd = f32c ? (const void*)g->invd32[axis] : (const void*)g->invd64[axis];
     const void* r = f32c ? (const void*)g->r32[axis] : (const void*)g->r64[axis];
+    const void* comp = f32c ? (const void*)g->comp32[axis] : (const void*)g->comp64[axis];
     hipEvent_t a;
     time_begin(g, 2 + axis, &a);
-    hipError_t e = launch_sweep(g->dtype, transposed, g->plan[axis], geo, in, out, invd, r, g->stream);
+    hipError_t e = launch_sweep(g->dtype, transposed, g->plan[axis], geo, in, out, invd, r, comp, g->comp_H[axis],
+                                g->stream);
     time_end(g, 2 + axis, a, geo.n * geo.inner * geo.outer);
     return e == hipSuccess ? BFVM_OK : hip_fail(e, "sweep kernel");
 }
@@ -414,6 +435,8 @@ int bfvm_destroy(bfvm_grid g)
         dfree(g->r64[a]);
         dfree(g->invd32[a]);
         dfree(g->r32[a]);
+        dfree(g->comp64[a]);
+        dfree(g->comp32[a]);
         if (g->work[a]) (void)hipFree(g->work[a]);
     }
     dfree(g->src_vox);
@@ -464,12 +487,32 @@ int bfvm_set_params(bfvm_grid g, const double* D, const double* lambda, double d
         invd32[a].assign(invd[a].begin(), invd[a].end());
         r32[a].assign(r[a].begin(), r[a].end());
     }
+    // exact compressed tables, [s][H + 2]
+    int compH[3];
+    std::vector<double> comp[3];
+    std::vector<float> comp32[3];
+    for (int a = 0; a < 3; ++a) {
+        compH[a] = comp_head(invd[a], ns[a], S);
+        if (compH[a] < 0) continue;
+        const int H = compH[a];
+        comp[a].resize((size_t)S * (H + 2));
+        for (int s = 0; s < S; ++s) {
+            for (int i = 0; i < H; ++i) comp[a][(size_t)s * (H + 2) + i] = invd[a][(size_t)i * S + s];
+            comp[a][(size_t)s * (H + 2) + H] = invd[a][(size_t)H * S + s];
+            comp[a][(size_t)s * (H + 2) + H + 1] = invd[a][(size_t)(ns[a] - 1) * S + s];
+        }
+        comp32[a].assign(comp[a].begin(), comp[a].end());
+    }
     for (int a = 0; a < 3; ++a) {
         int st;
         if ((st = dalloc_copy(g->invd64[a], invd[a].data(), invd[a].size(), g->stream))) return st;
         if ((st = dalloc_copy(g->r64[a], r[a].data(), r[a].size(), g->stream))) return st;
         if ((st = dalloc_copy(g->invd32[a], invd32[a].data(), invd32[a].size(), g->stream))) return st;
         if ((st = dalloc_copy(g->r32[a], r32[a].data(), r32[a].size(), g->stream))) return st;
+        g->comp_H[a] = -1;
+        if ((st = dalloc_copy(g->comp64[a], comp[a].data(), comp[a].size(), g->stream))) return st;
+        if ((st = dalloc_copy(g->comp32[a], comp32[a].data(), comp32[a].size(), g->stream))) return st;
+        g->comp_H[a] = compH[a];
     }
     g->D.assign(D, D + S);
     g->lambda.assign(lambda, lambda + S);
@@ -653,6 +696,28 @@ int bfvm_step_adjoint(bfvm_grid g, const void* field_in, void* grad, double* gra
         }
     }
     return BFVM_OK;
+}
+
+int bfvm_fill_uniform(bfvm_grid g, void* field, uint64_t seed, uint32_t stream, double lo, double hi)
+{
+    if (int st = check_grid(g)) return st;
+    if (!field) return fail(BFVM_EINVAL, "NULL field");
+    if (!std::isfinite(lo) || !std::isfinite(hi) || hi < lo) return fail(BFVM_EINVAL, "bounds must be finite, lo <= hi");
+    hipError_t e = launch_fill_uniform(g->dtype, field, g->nelem(), seed, stream, lo, hi, g->stream);
+    return e == hipSuccess ? BFVM_OK : hip_fail(e, "fill kernel");
+}
+
+int bfvm_fill_gaussian(bfvm_grid g, void* field, double cx, double cy, double cz, double sigma, double peak,
+                       double noise, uint64_t seed, uint32_t stream)
+{
+    if (int st = check_grid(g)) return st;
+    if (!field) return fail(BFVM_EINVAL, "NULL field");
+    for (double v : {cx, cy, cz, sigma, peak, noise})
+        if (!std::isfinite(v)) return fail(BFVM_EINVAL, "non-finite argument");
+    if (!(sigma > 0)) return fail(BFVM_EINVAL, "sigma must be > 0");
+    hipError_t e = launch_fill_gaussian(g->dtype, field, g->nx, g->ny, g->nz, g->S, cx, cy, cz, sigma, peak, noise,
+                                        seed, stream, g->stream);
+    return e == hipSuccess ? BFVM_OK : hip_fail(e, "fill kernel");
 }
 
 int bfvm_read_field(bfvm_grid g, const void* field, void* host_dst)

@@ -72,9 +72,10 @@ SweepPlan default_plan(int axis, const AxisGeom& g, int dtype);
 // Enqueue one sweep (forward Thomas, or transposed solve when transposed) of
 // field `in` into `out` (may alias) on `stream`.  coefs point to double or
 // float tables matching the dtype's compute type.
+// comp / comp_H: the axis's exact compressed coefficient table (comp_H < 0: none)
 hipError_t launch_sweep(int dtype, bool transposed, const SweepPlan& plan, const AxisGeom& g,
                         const void* in, void* out, const void* invd, const void* r,
-                        hipStream_t stream);
+                        const void* comp, int comp_H, hipStream_t stream);
 
 // Sparse stages.
 hipError_t launch_source(int dtype, void* u, const int64_t* vox, const double* P,
@@ -93,6 +94,13 @@ hipError_t launch_adjoint_reduce(int dtype, const void* y, const void* x, const 
                                  int64_t nelem, double* partials, int64_t max_blocks,
                                  double* out, hipStream_t stream);
 int64_t adjoint_reduce_blocks(int64_t nvox);
+
+// Device-side field set-up (fill.hip).
+hipError_t launch_fill_uniform(int dtype, void* u, int64_t n, uint64_t seed, uint32_t stream, double lo, double hi,
+                               hipStream_t st);
+hipError_t launch_fill_gaussian(int dtype, void* u, int64_t nx, int64_t ny, int64_t nz, int S, double cx, double cy,
+                                double cz, double sigma, double peak, double noise, uint64_t seed, uint32_t stream,
+                                hipStream_t st);
 
 }  // namespace bfvm
 
@@ -114,6 +122,11 @@ struct bfvm_grid_s {
     double* r64[3] = {nullptr, nullptr, nullptr};
     float* invd32[3] = {nullptr, nullptr, nullptr};
     float* r32[3] = {nullptr, nullptr, nullptr};
+    // exact compressed coefficient tables, [s][H + 2] (head, constant, last);
+    // comp_H[a] < 0: the axis has none (the full table is used)
+    double* comp64[3] = {nullptr, nullptr, nullptr};
+    float* comp32[3] = {nullptr, nullptr, nullptr};
+    int comp_H[3] = {-1, -1, -1};
 
     // merged sources (device)
     int64_t nsrc = 0;

@@ -159,11 +159,15 @@ __device__ __forceinline__ void stage_table(C* tab, const C* __restrict__ invd, 
 
 // AX (0, 1, 2) only names the axis in the kernel symbol, so that profiles
 // report the x, y and z sweeps separately.
-template <typename T, typename C, int M, bool TR, bool LDS_TAB, bool XROWS, int AX>
+// COEF: where the Thomas constants come from: 0 the global [n][S] table,
+// 1 its LDS copy in [s][segment][k] layout, 2 rows built in LDS from the
+// exact compressed table comp ([s][H + 2]: head, interior constant, last
+// slot), so that a segment inside the constant interior needs no table.
+template <typename T, typename C, int M, bool TR, int COEF, bool XROWS, int AX>
 __global__ __launch_bounds__(1024) void k_sweep_seg_strided(const T* in, T* out, AxisGeom g,
                                                             const C* __restrict__ invd,
                                                             const C* __restrict__ rr, int lpw, int SP,
-                                                            FastDiv divS)
+                                                            FastDiv divS, const C* __restrict__ comp, int H)
 {
     uint32_t bx, by;
     xcd_tile(bx, by);
@@ -204,10 +208,34 @@ __global__ __launch_bounds__(1024) void k_sweep_seg_strided(const T* in, T* out,
     }
     const C r = rr[s];
     const C prev = (TR && i0 > 0 && last >= 0) ? invd[(i0 - 1) * S + s] : (C)0;
-    if (LDS_TAB) {
+    if (COEF == 1) {
         stage_table<C, M>(tab, invd, (uint32_t)g.n, (uint32_t)(K * M), (uint32_t)S, (uint32_t)SP, divS);
         __syncthreads();
         LdsCoef<C> coef{tab + s * SP + seg * (M + 1), prev};
+        solve_segment<C, M, TR, false>(v, seg, K, line, lpw, r, coef, sc, true);
+    } else if (COEF == 2) {
+        // rows of M + 1 slots per substrate: the nh segments that overlap the
+        // head, one row of the interior constant (every other segment before
+        // the last slot's), the segment holding slot n - 1, and a zero row for
+        // segments past the line end; built from comp ([s][H + 2])
+        const int nh = (H + M - 1) / M;
+        const int nm1 = (int)g.n - 1;
+        const int tseg = nm1 / M;
+        const int RW = M + 1, SPr = (nh + 3) * RW;
+        for (int e = threadIdx.x; e < S * SPr; e += blockDim.x) {
+            const int ss = e / SPr, q = e - ss * SPr, row = q / RW, k = q - row * RW;
+            const C* cp = comp + ss * (H + 2);
+            const int i = row < nh ? row * M + k : tseg * M + k;
+            C val = (C)0;
+            if (k < M && row != nh + 2) {
+                if (row == nh) val = cp[H];
+                else val = i < H ? cp[i] : (i < nm1 ? cp[H] : (i == nm1 ? cp[H + 1] : (C)0));
+            }
+            tab[e] = val;
+        }
+        __syncthreads();
+        const int row = seg < nh ? seg : (seg == tseg ? nh + 1 : (seg > tseg ? nh + 2 : nh));
+        LdsCoef<C> coef{tab + s * SPr + row * RW, prev};
         solve_segment<C, M, TR, false>(v, seg, K, line, lpw, r, coef, sc, true);
     } else {
         GlobalCoef<C> coef{invd + (last >= 0 ? i0 * S + s : s), S, (int)(last < M ? last : M), prev};
@@ -557,11 +585,9 @@ std::string check_plan(const SweepPlan& p, const AxisGeom& g, int dtype)
         const int64_t K = (int64_t)p.w * 64 / p.lpw;
         if (K * p.m < g.n) return "too few segments for the line length";
         if (ceil_div(g.outer * g.S, p.lpw) >= (1ll << 31)) return "too many lines";
-        const int period = cs == 8 ? 16 : 32;
-        const int64_t KM1 = K * (p.m + 1);
-        const int64_t SP = KM1 + (((64 / p.lpw - KM1) % period) + period) % period;
-        if ((4 * (int64_t)scan_slots((int)K, p.lpw, p.w * 64, false) + g.S * SP) * cs > max_lds())
-            return "LDS too large (coefficient table)";
+        // the coefficient table itself need not fit: the launch then uses the
+        // compressed rows or the global table
+        if (4 * (int64_t)scan_slots((int)K, p.lpw, p.w * 64, false) * cs > max_lds()) return "LDS too large";
         if (K * p.m * g.S >= (1 << 24)) return "line too long";
         return "";
     }
@@ -713,7 +739,7 @@ static hipError_t launch_xpipe(const SweepPlan& p, const AxisGeom& g, const T* i
 
 template <typename T, typename C, bool TR, int M>
 static hipError_t launch_seg(const SweepPlan& p, const AxisGeom& g, const T* in, T* out,
-                             const C* invd, const C* r, hipStream_t st)
+                             const C* invd, const C* r, const C* comp, int compH, hipStream_t st)
 {
     if (p.kind == PLAN_SEG_STRIDED || p.kind == PLAN_SEG_XROWS) {
         const bool xrows = p.kind == PLAN_SEG_XROWS;
@@ -736,19 +762,40 @@ static hipError_t launch_seg(const SweepPlan& p, const AxisGeom& g, const T* in,
         const size_t tab = (size_t)g.S * SP * sizeof(C);
         const int64_t KMS = (int64_t)K * M * g.S;
         const bool lds_tab = scan + tab <= (size_t)max_lds() && KMS < (1 << 24) && KMS * g.S <= (1ll << 40);
+        // The exact compressed table replaces a full table that would not fit,
+        // or that would take more than 48 KB of LDS (fewer workgroups per CU).
+        // compressed rows: head segments, constant, last slot's segment, zero;
+        // usable when the head segments end before the last slot's segment
+        const int nh = compH >= 0 ? (compH + M - 1) / M : 0;
+        const bool comp_ok = comp && compH >= 0 && (g.n - 1) / M >= nh;
+        const size_t ctab = comp_ok ? (size_t)g.S * (nh + 3) * (M + 1) * sizeof(C) : 0;
+        const bool use_comp = ctab > 0 && scan + ctab <= (size_t)max_lds() && (!lds_tab || tab > (48u << 10));
         const bool zaxis = g.axis == 2;
-        if (xrows)
-            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, true, true, 0>), grid, dim3(threads), scan + tab,
-                               st, in, out, gg, invd, r, p.lpw, SP, FastDiv((uint32_t)g.S));
+        const FastDiv dS((uint32_t)g.S);
+        if (xrows && use_comp)
+            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 2, true, 0>), grid, dim3(threads), scan + ctab, st,
+                               in, out, gg, invd, r, p.lpw, SP, dS, comp, compH);
+        else if (xrows && lds_tab)
+            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 1, true, 0>), grid, dim3(threads), scan + tab, st,
+                               in, out, gg, invd, r, p.lpw, SP, dS, comp, compH);
+        else if (xrows)
+            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 0, true, 0>), grid, dim3(threads), scan, st, in,
+                               out, gg, invd, r, p.lpw, SP, dS, comp, compH);
+        else if (use_comp && zaxis)
+            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 2, false, 2>), grid, dim3(threads), scan + ctab,
+                               st, in, out, gg, invd, r, p.lpw, SP, dS, comp, compH);
+        else if (use_comp)
+            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 2, false, 1>), grid, dim3(threads), scan + ctab,
+                               st, in, out, gg, invd, r, p.lpw, SP, dS, comp, compH);
         else if (lds_tab && zaxis)
-            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, true, false, 2>), grid, dim3(threads), scan + tab,
-                               st, in, out, gg, invd, r, p.lpw, SP, FastDiv((uint32_t)g.S));
+            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 1, false, 2>), grid, dim3(threads), scan + tab, st,
+                               in, out, gg, invd, r, p.lpw, SP, dS, comp, compH);
         else if (lds_tab)
-            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, true, false, 1>), grid, dim3(threads), scan + tab,
-                               st, in, out, gg, invd, r, p.lpw, SP, FastDiv((uint32_t)g.S));
+            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 1, false, 1>), grid, dim3(threads), scan + tab, st,
+                               in, out, gg, invd, r, p.lpw, SP, dS, comp, compH);
         else
-            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, false, false, 1>), grid, dim3(threads), scan, st,
-                               in, out, gg, invd, r, p.lpw, SP, FastDiv((uint32_t)g.S));
+            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 0, false, 1>), grid, dim3(threads), scan, st, in,
+                               out, gg, invd, r, p.lpw, SP, dS, comp, compH);
     } else {
         const int K = (int)ceil_div(g.n, M);
         const int SB = xtile_sb(M, g.S, (int)sizeof(T));
@@ -769,12 +816,13 @@ static hipError_t launch_seg(const SweepPlan& p, const AxisGeom& g, const T* in,
 
 template <typename T, typename C, bool TR>
 static hipError_t launch_typed(const SweepPlan& p, const AxisGeom& g, const void* in, void* out,
-                               const void* invd, const void* r, hipStream_t st)
+                               const void* invd, const void* r, const void* comp, int compH, hipStream_t st)
 {
     const T* i = static_cast<const T*>(in);
     T* o = static_cast<T*>(out);
     const C* cf = static_cast<const C*>(invd);
     const C* rr = static_cast<const C*>(r);
+    const C* cc = static_cast<const C*>(comp);
     if (p.kind == PLAN_LINE) {
         const int64_t lines = g.inner * g.outer;
         hipLaunchKernelGGL((k_sweep_line<T, C, TR>), dim3((unsigned)ceil_div(lines, 256)), dim3(256), 0,
@@ -782,28 +830,29 @@ static hipError_t launch_typed(const SweepPlan& p, const AxisGeom& g, const void
         return hipGetLastError();
     }
     switch (p.m) {
-        case 4: return launch_seg<T, C, TR, 4>(p, g, i, o, cf, rr, st);
-        case 8: return launch_seg<T, C, TR, 8>(p, g, i, o, cf, rr, st);
-        case 16: return launch_seg<T, C, TR, 16>(p, g, i, o, cf, rr, st);
-        case 32: return launch_seg<T, C, TR, 32>(p, g, i, o, cf, rr, st);
+        case 4: return launch_seg<T, C, TR, 4>(p, g, i, o, cf, rr, cc, compH, st);
+        case 8: return launch_seg<T, C, TR, 8>(p, g, i, o, cf, rr, cc, compH, st);
+        case 16: return launch_seg<T, C, TR, 16>(p, g, i, o, cf, rr, cc, compH, st);
+        case 32: return launch_seg<T, C, TR, 32>(p, g, i, o, cf, rr, cc, compH, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_sweep(int dtype, bool transposed, const SweepPlan& plan, const AxisGeom& g,
-                        const void* in, void* out, const void* invd, const void* r, hipStream_t st)
+                        const void* in, void* out, const void* invd, const void* r, const void* comp, int compH,
+                        hipStream_t st)
 {
     if (g.inner * g.outer == 0) return hipSuccess;
     switch (dtype) {
         case DT_F64:
-            return transposed ? launch_typed<double, double, true>(plan, g, in, out, invd, r, st)
-                              : launch_typed<double, double, false>(plan, g, in, out, invd, r, st);
+            return transposed ? launch_typed<double, double, true>(plan, g, in, out, invd, r, comp, compH, st)
+                              : launch_typed<double, double, false>(plan, g, in, out, invd, r, comp, compH, st);
         case DT_F32:
-            return transposed ? launch_typed<float, double, true>(plan, g, in, out, invd, r, st)
-                              : launch_typed<float, double, false>(plan, g, in, out, invd, r, st);
+            return transposed ? launch_typed<float, double, true>(plan, g, in, out, invd, r, comp, compH, st)
+                              : launch_typed<float, double, false>(plan, g, in, out, invd, r, comp, compH, st);
         case DT_F32_FAST:
-            return transposed ? launch_typed<float, float, true>(plan, g, in, out, invd, r, st)
-                              : launch_typed<float, float, false>(plan, g, in, out, invd, r, st);
+            return transposed ? launch_typed<float, float, true>(plan, g, in, out, invd, r, comp, compH, st)
+                              : launch_typed<float, float, false>(plan, g, in, out, invd, r, comp, compH, st);
         default:
             return hipErrorInvalidValue;
     }

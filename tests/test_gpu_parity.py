@@ -139,6 +139,41 @@ def test_fused_and_plain_schedules_agree_bitwise():
     assert np.array_equal(a, c)
 
 
+@pytest.mark.parametrize("shape", [(1000, 20, 24), (24, 1000, 20), (20, 24, 1000)])
+@pytest.mark.parametrize("dtype,tol", [("f64", F64_TOL), ("f32", F32_TOL)])
+def test_compressed_coefficient_rows(shape, dtype, tol):
+    # 1000-long lines with 8 substrates: the full LDS coefficient table of
+    # the strided kernel would take more than 48 KB, so the sweep along the
+    # long axis builds its coefficient rows from the exact compressed table
+    # (head, interior constant, last slot); D up to 1e5 keeps the head short
+    S = 8
+    p = small_problem(shape, S, seed=450 + shape.index(1000), nsrc=500, ndir=60, nsteps=2)
+    ref = oracle_run(p)
+    got = gpu_run(p, dtype=dtype)
+    emax, _ = rel_err(got, ref)
+    assert emax <= tol, (shape, dtype, emax)
+
+
+def test_x_rows_with_the_global_coefficient_table():
+    # 2000-voxel rows x 8 substrates with r = 1e5: the constants do not settle
+    # within 512 slots (no compressed form) and the full table exceeds the
+    # LDS, so the x rows read their constants from the global table
+    S = 8
+    p = small_problem((2000, 3, 2), S, seed=470, nsrc=40, ndir=8, nsteps=2)
+    p.D = np.full(S, 1e9)
+    # bar: each of the 6 solves (2 steps x 3 axes) may amplify the rounding
+    # difference between the reciprocal-multiply and the oracle's division by
+    # cond(A) <= 1 + 4r (r = 1e5 on x); the other axes are far better
+    # conditioned, so 6 (1 + 4r) 2^-53 bounds the whole run
+    r = p.dt * p.D[0] / p.h[0] ** 2
+    tol = 6 * (1 + 4 * r) * 2.0 ** -53
+    ref = oracle_run(p)
+    got = gpu_run(p)
+    emax, _ = rel_err(got, ref)
+    print(f"r = {r:.3g}: e_max = {emax:.3e} (bar {tol:.2e})")
+    assert emax <= tol, emax
+
+
 def test_line_kernel_all_axes():
     p = small_problem(NONCUBIC, 2, seed=400, nsrc=100, ndir=10, nsteps=2)
     plans = {a: (0, 0, 0, 0) for a in range(3)}

@@ -270,6 +270,27 @@ def config(k: int, *, n: Optional[int] = None, nsub: Optional[int] = None,
     return p
 
 
+# Table 1 cases beyond the 1000^3 x 4 cube, at 10 um: (side, substrates, storage)
+LARGE_CASES = {
+    "liver12": (1500, 8, "f64"),    # "12.5% liver": 1500^3 x 8, 216 GB in FP64
+    "liver16": (2000, 8, "f32"),    # "16.6% liver": 2000^3 x 8, 256 GB in FP32 (512 GB in FP64)
+}
+
+
+def large_config(name: str, n_sources: int = 1_000_000, nsteps: int = 5) -> Problem:
+    """A Table 1 cube with the tumour-scale recipe (D log-uniform in [1e3, 1e5],
+    lambda in [0.01, 0.1], dt = 0.01, distinct source voxels with the 256^3
+    workload's rates).  No host field: the field is written on the device
+    with the same seeded uniform stream (seed, stream 0)."""
+    side, S, dtype = LARGE_CASES[name]
+    seed = 1100 + side // 100
+    D, L = random_coefficients(seed, S, (3.0, 5.0), (0.01, 0.1))
+    p = Problem(f"{name}-{side}^3x{S}-{dtype}", side, side, side, S, np.array([10.0] * 3), D, L, 0.01,
+                nsteps, seed, dtype=dtype)
+    p.src = make_sources(seed, p.V, S, n_sources)
+    return p
+
+
 def target_field(p: Problem) -> np.ndarray:
     return uniform(p.seed, 4, int(np.prod(p.shape))).reshape(p.shape)
 
