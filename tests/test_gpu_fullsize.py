@@ -65,6 +65,52 @@ def test_eigenmode_full_size_sampled():
     assert err <= 1e-12
 
 
+@pytest.mark.parametrize("case,tol", [("liver12", 1e-12), ("liver16", (1 + 12 * 3) * 2.0 ** -24)])
+def test_eigenmode_large_table1_cubes(case, tol):
+    # the 1500^3 x 8 (FP64, 216 GB) and 2000^3 x 8 (FP32, 256 GB) cubes, the
+    # benchmark's default plans (compressed coefficient rows on every axis):
+    # a DCT-II eigenmode decays by prod_a mu_a^-m at any size.  FP32 bar: the
+    # rounded initial field and 4 stores per step, each within 2^-24, carried
+    # through contractive solves: (1 + 12 m) 2^-24 for m = 3
+    import torch
+    p = workloads.large_config(case)
+    p.src = None
+    n = p.nx
+    ks = (2, 3, 1)
+    m = 3
+    dev = "cuda"
+    g = make_grid(p, p.dtype)
+    c = [torch.cos(np.pi * k * (torch.arange(n, dtype=torch.float64, device=dev) + 0.5) / n) for k in ks]
+    u = torch.empty(p.shape, dtype=g.torch_dtype, device=dev)
+    for z0 in range(0, n, 50):
+        z1 = min(n, z0 + 50)
+        blk = c[2][z0:z1, None, None, None] * c[1][None, :, None, None] * c[0][None, None, :, None]
+        u[z0:z1] = blk.to(g.torch_dtype).expand(z1 - z0, n, n, p.S)
+        del blk
+    g.step(u, m)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(4)
+    cnt = 1_000_000
+    idx = rng.integers(0, n, (cnt, 3))
+    s = rng.integers(0, p.S, cnt)
+    it = torch.from_numpy(idx).to(dev)
+    got = u[it[:, 2], it[:, 1], it[:, 0], torch.from_numpy(s).to(dev)].double().cpu().numpy()
+    g.close()
+    del u
+    _free()
+    base = np.ones(cnt)
+    for a, k in enumerate(ks):
+        base = base * np.cos(np.pi * k * (idx[:, a] + 0.5) / n)
+    fac = np.ones(p.S)
+    for a, k in enumerate(ks):
+        r = p.dt * p.D / p.h[a] ** 2
+        beta = p.dt * p.lam / 3.0
+        fac *= (1.0 + beta + 4.0 * r * np.sin(np.pi * k / (2.0 * n)) ** 2) ** (-m)
+    err = np.max(np.abs(got - base * fac[s]))
+    print(f"eigenmode {p.name}, {m} steps: max abs err {err:.3e} (bar {tol:.1e})")
+    assert err <= tol
+
+
 _REF = {}
 
 
