@@ -147,3 +147,27 @@ def test_tumour_scale_20_steps_vs_oracle(dtype, tol):
     emax, e2 = rel_err(got[..., None], ref[..., None])
     print(f"1000^3x4 {dtype}, substrate {s} (D={p.D[s]:.3g}), {p.nsteps} steps: e_max={emax:.3e} e_2={e2:.3e}")
     assert emax <= tol
+
+
+def test_endtoend_pipeline_matches_oracle():
+    # the end-to-end run at full size (500^3 x 1, 1000 agents), 10 of its 500
+    # steps: Gaussian profile written on the device, agents as bulk
+    # sources and sinks, against the oracle started from the host profile
+    import torch
+    import paper_2602_05017_amd as bf
+    p = workloads.endtoend_config(nsteps=10)
+    g = bf.Grid(p.nx, p.ny, p.nz, p.S, tuple(p.h), dtype="f64")
+    g.set_params(p.D, p.lam, p.dt)
+    u = torch.empty(p.shape, dtype=torch.float64, device="cuda")
+    g.fill_gaussian(u, (p.nx / 2.0, p.ny / 2.0, p.nz / 2.0), p.gauss_sigma, peak=1.0, noise=p.gauss_noise,
+                    seed=p.seed)
+    g.set_sources(p.src.voxel, p.src.secretion, p.src.saturation, p.src.uptake)
+    g.step(u, p.nsteps)
+    got = g.read_field(u)
+    g.close()
+    ref = np.array(p.u0, copy=True)
+    src = oracle.Sources(p.src.voxel, p.src.secretion, p.src.saturation, p.src.uptake)
+    oracle.step(ref, p.h, p.D, p.lam, p.dt, src, None, p.nsteps)
+    emax, e2 = rel_err(got, ref)
+    print(f"end-to-end 500^3, 10 steps: e_max={emax:.3e} e_2={e2:.3e}")
+    assert emax <= 1e-12

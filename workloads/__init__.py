@@ -142,6 +142,8 @@ class Problem:
     u0: Optional[np.ndarray] = None   # [nz, ny, nx, S] float64 (None: generate lazily)
     u0_kind: str = "uniform"          # "uniform" or "gaussian"
     dtype: str = "f64"
+    gauss_sigma: float = 8.0          # Gaussian profile: sigma (voxels) and noise amplitude
+    gauss_noise: float = 0.01
 
     @property
     def V(self):
@@ -186,16 +188,17 @@ def make_sources(seed: int, V: int, S: int, count: int) -> SourceList:
 def make_field(p: Problem) -> np.ndarray:
     nz, ny, nx, S = p.shape
     if p.u0_kind == "gaussian":
-        # Gaussian blob, sigma 8 voxels, peak 1 at the centre (voxel-centre
-        # coordinates i + 1/2), plus 0.01 * U[0,1) noise.
-        sig = 8.0
+        # Gaussian blob (sigma 8 voxels unless set), peak 1 at the centre
+        # (voxel-centre coordinates i + 1/2), plus noise * U[0,1) (0.01 unless set)
+        sig = p.gauss_sigma
         cz, cy, cx = nz / 2.0, ny / 2.0, nx / 2.0
         z = (np.arange(nz) + 0.5 - cz)[:, None, None]
         y = (np.arange(ny) + 0.5 - cy)[None, :, None]
         x = (np.arange(nx) + 0.5 - cx)[None, None, :]
         g = np.exp(-(x * x + y * y + z * z) / (2.0 * sig * sig))
         u = np.repeat(g[..., None], S, axis=3)
-        u += 0.01 * uniform(p.seed, 0, u.size).reshape(u.shape)
+        if p.gauss_noise:
+            u += p.gauss_noise * uniform(p.seed, 0, u.size).reshape(u.shape)
         return np.ascontiguousarray(u)
     u = np.empty(p.shape, dtype=np.float64)
     if u.size > (1 << 22):
@@ -265,6 +268,28 @@ def config(k: int, *, n: Optional[int] = None, nsub: Optional[int] = None,
             p.src = make_sources(seed, V, S, min(n_sources, V))
     else:
         raise ValueError("config k must be 1..4 (batches: batch_config)")
+    if with_field:
+        p.field()
+    return p
+
+
+def endtoend_config(nsteps: int = 500, with_field: bool = True) -> Problem:
+    """The paper's end-to-end run (Sec. 5.3): a 5 mm cube at 10 um (500^3), one
+    substrate, a Gaussian initial profile, 500 bulk-source agents and 500
+    uptake-sink agents in distinct seeded voxels, 500 steps of 0.01 min.
+    Unstated values chosen here: D = 1e5 um^2/min, lambda = 0.1 /min (the
+    64^3 case's), sigma = 62.5 voxels (1/8 of the side, as 8 of 64), no
+    noise, sources secrete 10 /min towards saturation 1, sinks take up
+    10 /min."""
+    side, seed = 500, 1010
+    p = Problem("endtoend-500^3x1", side, side, side, 1, np.array([10.0] * 3), np.array([1.0e5]),
+                np.array([0.1]), 0.01, nsteps, seed, u0_kind="gaussian", gauss_sigma=side / 8.0, gauss_noise=0.0)
+    vox = distinct_voxels(seed, 2, p.V, 1000)
+    sec = np.zeros((1000, 1))
+    upt = np.zeros((1000, 1))
+    sec[:500, 0] = 10.0          # bulk sources
+    upt[500:, 0] = 10.0          # uptake sinks
+    p.src = SourceList(vox, sec, np.ones((1000, 1)), upt)
     if with_field:
         p.field()
     return p
