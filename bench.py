@@ -396,6 +396,7 @@ def run_large(args):
                         "elements_per_launch": elems / n if n else 0}
     g.timing(False)
     plans = [g.get_plan(a) for a in range(3)]
+    lib_bytes = g.device_bytes()
     g.close()
     ms_step = 1e3 * t / steps
     value = upd * steps / t
@@ -416,6 +417,8 @@ def run_large(args):
                      "algorithmic_bytes_per_launch": alg, "avg_launch_ms": round(sweeps[dom]["avg_ms"], 4),
                      "step_alg_GBps": round(3 * 2 * e * upd / (ms_step * 1e-3) / 1e9, 1),
                      "stages_ms_per_step": {k: round(v["total_ms"] / steps, 3) for k, v in stages.items()}},
+        "memory": {"field_bytes": upd * e, "library_bytes": lib_bytes,
+                   "bytes_per_voxel_substrate": round((upd * e + lib_bytes) / upd, 3)},
         "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
@@ -549,6 +552,9 @@ def main():
                 "schedule": {"fused_yz_slabs": sched[0] == 1, "slab_width": sched[1]},
                 "stages_ms_per_step": {k: round(v["total_ms"] / args.steps, 4) for k, v in stages.items()}}
     fp64_ref = u[..., 0].flatten()[:: 997].double().cpu() if not args.no_fp32 else None
+    lib_bytes = g.device_bytes()
+    memory = {"field_bytes": upd_per_step * 8, "library_bytes": lib_bytes,
+              "bytes_per_voxel_substrate": round((upd_per_step * 8 + lib_bytes) / upd_per_step, 3)}
     g.close()
     del u
     torch.cuda.empty_cache()
@@ -596,6 +602,7 @@ def main():
                    "h_um": list(map(float, p.h))},
         "roofline": roofline,
         "fp32": fp32,
+        "memory": memory,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -132,6 +132,12 @@ int bfvm_sweep(bfvm_grid g, void* field, int32_t axis);
 int bfvm_step_adjoint(bfvm_grid g, const void* field_in, void* grad,
                       double* grad_D, double* grad_lambda);
 
+/* Device memory the library holds for this grid (coefficient tables, source
+ * and Dirichlet lists, adjoint workspace once allocated), in bytes, as the
+ * HIP runtime sizes the allocations; the caller-owned fields are not
+ * included.  Errors: EINVAL. */
+int bfvm_device_bytes(bfvm_grid g, int64_t* bytes);
+
 /* ---- device-side field set-up ----------------------------------------- */
 /* Fill a device field of this grid with seeded uniform values in [lo, hi):
  * element i (layout index) = lo + (hi - lo) * U_i, where U_i = (key_i >> 11)

@@ -30,7 +30,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ERANGE", -3: "ESTATE", -4: "EDEVICE", -5: 
 EXPORTS = [
     "bfvm_create", "bfvm_destroy", "bfvm_set_stream", "bfvm_set_params", "bfvm_set_sources",
     "bfvm_set_dirichlet", "bfvm_step", "bfvm_sweep", "bfvm_step_adjoint", "bfvm_read_field",
-    "bfvm_fill_uniform", "bfvm_fill_gaussian",
+    "bfvm_fill_uniform", "bfvm_fill_gaussian", "bfvm_device_bytes",
     "bfvm_timing_enable", "bfvm_timing_read", "bfvm_timing_reset", "bfvm_timing_elements",
     "bfvm_set_schedule", "bfvm_get_schedule", "bfvm_get_plan", "bfvm_set_plan",
     "bfvm_batch_create", "bfvm_batch_destroy", "bfvm_batch_set_mode", "bfvm_batch_set_fields", "bfvm_batch_step",
@@ -231,6 +231,12 @@ class Grid:
         self._sync_stream()
         _check(lib().bfvm_step_adjoint(self._handle, pin, pg, _ptr(gD), _ptr(gL)), "bfvm_step_adjoint")
         return gD, gL
+
+    def device_bytes(self) -> int:
+        """Device memory held by the library for this grid (fields excluded)."""
+        b = ctypes.c_int64()
+        _check(lib().bfvm_device_bytes(self._handle, ctypes.byref(b)), "bfvm_device_bytes")
+        return b.value
 
     def fill_uniform(self, field, seed: int, stream: int = 0, lo: float = 0.0, hi: float = 1.0):
         """Seeded uniform values in [lo, hi) written on the device (SplitMix64 counter stream)."""

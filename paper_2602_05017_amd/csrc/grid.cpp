@@ -698,6 +698,34 @@ int bfvm_step_adjoint(bfvm_grid g, const void* field_in, void* grad, double* gra
     return BFVM_OK;
 }
 
+int bfvm_device_bytes(bfvm_grid g, int64_t* bytes)
+{
+    if (int st = check_grid(g)) return st;
+    if (!bytes) return fail(BFVM_EINVAL, "NULL pointer");
+    int64_t total = 0;
+    auto add = [&](const void* p) {
+        if (!p) return;
+        void* base = nullptr;
+        size_t size = 0;
+        if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) == hipSuccess) total += (int64_t)size;
+    };
+    for (int a = 0; a < 3; ++a) {
+        add(g->invd64[a]);
+        add(g->r64[a]);
+        add(g->invd32[a]);
+        add(g->r32[a]);
+        add(g->comp64[a]);
+        add(g->comp32[a]);
+        add(g->work[a]);
+    }
+    for (const void* p : {(const void*)g->src_vox, (const void*)g->src_P, (const void*)g->src_invQ,
+                          (const void*)g->dir_elem, (const void*)g->dir_val, (const void*)g->dir_elem_slab,
+                          (const void*)g->dir_val_slab, (const void*)g->red_partials, (const void*)g->red_out})
+        add(p);
+    *bytes = total;
+    return BFVM_OK;
+}
+
 int bfvm_fill_uniform(bfvm_grid g, void* field, uint64_t seed, uint32_t stream, double lo, double hi)
 {
     if (int st = check_grid(g)) return st;

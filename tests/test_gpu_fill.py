@@ -104,3 +104,18 @@ def test_fill_rejects_bad_arguments():
     with pytest.raises(bf.BfvmError):
         g.fill_gaussian(u, (4, float("nan"), 4), 1.0)
     g.close()
+
+
+def test_device_bytes_accounts_for_the_library_allocations():
+    import torch
+    p = small_problem((40, 30, 20), 3, seed=11, nsrc=100, ndir=10, nsteps=1)
+    g = make_grid(p, "f64")
+    n_tab = sum(n * p.S * (8 + 4) + p.S * (8 + 4) for n in (p.nx, p.ny, p.nz))   # invd64, invd32, r64, r32
+    b0 = g.device_bytes()
+    assert b0 >= n_tab
+    u = torch.from_numpy(p.u0).cuda()
+    gg = torch.zeros_like(u)
+    g.step_adjoint(u, gg)                       # allocates the three-field workspace
+    b1 = g.device_bytes()
+    assert b1 - b0 >= 3 * p.V * p.S * 8
+    g.close()
