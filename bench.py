@@ -501,6 +501,26 @@ def run_endtoend(args):
     print(json.dumps(line), flush=True)
 
 
+def rmw_ceiling(u, reps: int = 3):
+    """Practical HBM ceiling of a read+write pass: an in-place streaming
+    multiply by 1.0 (values unchanged) over the whole field, timed with events
+    on the current stream.  Every sweep reads and writes each element once, so
+    this bounds a sweep's algorithmic rate on this device."""
+    import torch
+    u.mul_(1.0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        u.mul_(1.0)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 2 * u.numel() * u.element_size()
+    return {"GBps": round(nbytes / (ms * 1e-3) / 1e9, 1), "kind": "in-place u *= 1.0 over the field (torch)",
+            "bytes": nbytes}
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -552,6 +572,10 @@ def main():
                 "schedule": {"fused_yz_slabs": sched[0] == 1, "slab_width": sched[1]},
                 "stages_ms_per_step": {k: round(v["total_ms"] / args.steps, 4) for k, v in stages.items()}}
     fp64_ref = u[..., 0].flatten()[:: 997].double().cpu() if not args.no_fp32 else None
+    roofline["practical_ceiling"] = rmw_ceiling(u)
+    roofline["frac_of_practical_ceiling"] = round(roofline["step_alg_GBps"] / roofline["practical_ceiling"]["GBps"], 4)
+    log(f"in-place read+write ceiling on the same field: {roofline['practical_ceiling']['GBps']:.0f} GB/s; "
+        f"the step runs at {roofline['frac_of_practical_ceiling']:.1%} of it")
     lib_bytes = g.device_bytes()
     memory = {"field_bytes": upd_per_step * 8, "library_bytes": lib_bytes,
               "bytes_per_voxel_substrate": round((upd_per_step * 8 + lib_bytes) / upd_per_step, 3)}

@@ -133,6 +133,19 @@ def test_default_plans_are_valid(L, shape, dtype):
     L.bfvm_destroy(g)
 
 
+def test_long_fp32_y_lines_use_full_cache_line_tiles(L):
+    # FP32 y lines of 1000 take 32-line tiles (128 bytes per row); z and FP64 keep 16
+    for dtype, y, z in ((1, (1, 32, 16, 32), (1, 32, 8, 16)), (2, (1, 32, 16, 32), (1, 32, 8, 16)),
+                        (0, (1, 32, 8, 16), (1, 32, 8, 16))):
+        st, g = _create(L, 1000, 1000, 1000, 4, dtype=dtype)
+        assert st == 0
+        assert _plan(L, g, 1) == y and _plan(L, g, 2) == z
+        L.bfvm_destroy(g)
+    st, g = _create(L, 64, 1500, 64, 1, dtype=1)          # 48 segments x 32 lines do not fit 16 waves
+    assert _plan(L, g, 1)[3] == 16
+    L.bfvm_destroy(g)
+
+
 def test_set_plan_rejects_plans_that_do_not_fit(L):
     st, g = _create(L, 100, 100, 100, 4)
     assert L.bfvm_set_plan(g, 1, 1, 8, 1, 16) == -1      # 4 segments x 8 < 100
