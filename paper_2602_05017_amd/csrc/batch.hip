@@ -13,7 +13,9 @@
 // split into one launch per (storage type, elements-per-thread) class, so
 // each launch runs a kernel compiled for exactly that register shape; the
 // lines per tile may differ between domains of a class.  A step is at most
-// 4 + 3 x (number of classes) launches, captured once and replayed.
+// 4 + 3 x (number of classes) launches, captured once and replayed.  The
+// launches of each storage type form an independent chain on a stream of its
+// own, so the chains of FP64 and FP32 domains overlap on the device.
 //
 // Persistent mode (switched off): ONE launch per step whose blocks take the
 // items of all stages from an atomic queue and wait, through per-(domain,
@@ -485,6 +487,10 @@ struct bfvm_batch_s {
     std::vector<BDomain> doms;        // host copy of the descriptors
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // side streams and events of the per-storage-type chains (grouped mode)
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_join[2] = {nullptr, nullptr};
     int mode = BFVM_BATCH_GROUPED;
     BDomain* d_doms = nullptr;
     int64_t chunk_elems = 1 << 14;    // work per item
@@ -753,22 +759,42 @@ int enqueue_program(bfvm_batch b, const Program& P)
         BHIP(hipGetLastError(), "batch kernel");
         return BFVM_OK;
     }
+    // Every launch covers domains of one storage type only, and every item
+    // touches its own domain's buffers (and its own reduction slots), so the
+    // launches of each storage type form an independent chain.  The chains
+    // run on their own streams, forked from and joined back into the batch
+    // stream (also under graph capture, where they become parallel branches),
+    // so that one chain's small or draining launches overlap the other's.
+    int chain_of[3] = {-1, -1, -1};
+    int nchain = 0;
+    for (const Launch& L : P.launches)
+        if (chain_of[L.dtype] < 0) chain_of[L.dtype] = nchain++;
+    const hipStream_t cs[3] = {b->stream, b->side[0], b->side[1]};
+    if (nchain > 1) {
+        BHIP(hipEventRecord(b->ev_fork, b->stream), "fork event");
+        for (int c = 1; c < nchain; ++c) BHIP(hipStreamWaitEvent(cs[c], b->ev_fork, 0), "fork wait");
+    }
     for (const Launch& L : P.launches) {
         const BItem* it = P.d_items + L.off;
+        const hipStream_t s = cs[chain_of[L.dtype]];
         if (!L.sweep) {
-            hipLaunchKernelGGL(k_group_sparse, dim3((unsigned)L.count), dim3(kBatchThreads), 0, b->stream,
-                               b->d_doms, it, b->d_partials);
+            hipLaunchKernelGGL(k_group_sparse, dim3((unsigned)L.count), dim3(kBatchThreads), 0, s, b->d_doms, it,
+                               b->d_partials);
         } else if (L.dtype == BFVM_F64) {
-            if (L.tr) launch_group_sweep<double, double, true>(L.M, L.count, b->stream, b->d_doms, it);
-            else launch_group_sweep<double, double, false>(L.M, L.count, b->stream, b->d_doms, it);
+            if (L.tr) launch_group_sweep<double, double, true>(L.M, L.count, s, b->d_doms, it);
+            else launch_group_sweep<double, double, false>(L.M, L.count, s, b->d_doms, it);
         } else if (L.dtype == BFVM_F32) {
-            if (L.tr) launch_group_sweep<float, double, true>(L.M, L.count, b->stream, b->d_doms, it);
-            else launch_group_sweep<float, double, false>(L.M, L.count, b->stream, b->d_doms, it);
+            if (L.tr) launch_group_sweep<float, double, true>(L.M, L.count, s, b->d_doms, it);
+            else launch_group_sweep<float, double, false>(L.M, L.count, s, b->d_doms, it);
         } else {
-            if (L.tr) launch_group_sweep<float, float, true>(L.M, L.count, b->stream, b->d_doms, it);
-            else launch_group_sweep<float, float, false>(L.M, L.count, b->stream, b->d_doms, it);
+            if (L.tr) launch_group_sweep<float, float, true>(L.M, L.count, s, b->d_doms, it);
+            else launch_group_sweep<float, float, false>(L.M, L.count, s, b->d_doms, it);
         }
         BHIP(hipGetLastError(), "grouped stage kernel");
+    }
+    for (int c = 1; c < nchain; ++c) {
+        BHIP(hipEventRecord(b->ev_join[c - 1], cs[c]), "join event");
+        BHIP(hipStreamWaitEvent(b->stream, b->ev_join[c - 1], 0), "join wait");
     }
     return BFVM_OK;
 }
@@ -864,6 +890,17 @@ int bfvm_batch_create(bfvm_batch* out, int32_t ndomains, const bfvm_grid* grids,
         }
         b->own_stream = true;
     }
+    for (int c = 0; c < 2; ++c) {   // default priority, like the batch stream
+        if (hipStreamCreateWithFlags(&b->side[c], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b->ev_join[c], hipEventDisableTiming) != hipSuccess) {
+            bfvm_batch_destroy(b);
+            return bfail(BFVM_EDEVICE, "side stream or event creation");
+        }
+    }
+    if (hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess) {
+        bfvm_batch_destroy(b);
+        return bfail(BFVM_EDEVICE, "fork event creation");
+    }
     b->grids.assign(grids, grids + ndomains);
     b->doms.resize(ndomains);
     std::memset(b->doms.data(), 0, sizeof(BDomain) * ndomains);
@@ -905,6 +942,14 @@ int bfvm_batch_destroy(bfvm_batch b)
     if (b->d_partials) (void)hipFree(b->d_partials);
     // d_counters is a slice of the uncached pool: never freed
     if (b->work_mem) (void)hipFree(b->work_mem);
+    for (int c = 0; c < 2; ++c) {
+        if (b->side[c]) {
+            (void)hipStreamSynchronize(b->side[c]);
+            (void)hipStreamDestroy(b->side[c]);
+        }
+        if (b->ev_join[c]) (void)hipEventDestroy(b->ev_join[c]);
+    }
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;
     return BFVM_OK;
