@@ -600,6 +600,23 @@ def main():
         g32.close()
         del u32
         torch.cuda.empty_cache()
+        # FP32 storage and FP32 sweeps (constants precomputed in FP64, rounded)
+        gf, uf, tf, stf = timed_run(p, "f32fast", args.steps, args.warmup, u_host)
+        vf = upd_per_step * args.steps / tf
+        sf = {k: v for k, v in stf.items() if k.startswith("sweep")}
+        df = max(sf, key=lambda k: sf[k]["total_ms"])
+        achf = 2 * 4 * sf[df]["elements_per_launch"] / (sf[df]["avg_ms"] * 1e-3) / 1e9
+        sampf = uf[..., 0].flatten()[:: 997].double().cpu()
+        errf = float((sampf - fp64_ref).abs().max() / fp64_ref.abs().max())
+        fp32["fp32_arithmetic"] = {"value": vf, "ms_per_step": round(1e3 * tf / args.steps, 3),
+                                   "dtype": "f32 storage, f32 arithmetic, f64-precomputed constants",
+                                   "dominant_kernel_GBps": round(achf, 1), "frac": round(achf / HBM_PEAK_GBPS, 4),
+                                   "max_rel_diff_vs_f64_sampled": errf}
+        log(f"f32 arithmetic: {fp32['fp32_arithmetic']['ms_per_step']} ms/step, {vf:.4g} updates/s, "
+            f"sampled diff vs f64 {errf:.2e}")
+        gf.close()
+        del uf
+        torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:
