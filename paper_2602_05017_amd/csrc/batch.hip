@@ -174,7 +174,7 @@ __device__ __forceinline__ void tile_solve_store(T* out, const TileSpot& t, int 
     const C* cf = invd + (t.last >= 0 ? i0 * S + t.s : t.s);
 #pragma unroll
     for (int k = 0; k < M; ++k) coef.b[k] = k <= t.last ? cf[(k <= t.last ? k : 0) * S] : (C)0;
-    solve_segment<C, M, TR, false>(v, seg, K, line, lpw, r, coef, sc, true);
+    solve_segment<C, M, TR, true>(v, seg, K, line, lpw, r, coef, sc, true);
     T* op = out + t.base;
     asm volatile("" : "+v"(op));
 #pragma unroll
@@ -306,7 +306,8 @@ template <typename T, typename C, int M, bool TR>
 __global__ __launch_bounds__(kBatchThreads, M <= 8 ? 4 : 2) void k_group_sweep(const BDomain* __restrict__ doms,
                                                                                const BItem* __restrict__ items)
 {
-    __shared__ __align__(16) C sc[4 * kBatchThreads];   // carry arrays
+    // carry arrays, lane-parallel layout: lpw * (K + 1) = 512 + lpw <= 576 slots each
+    __shared__ __align__(16) C sc[4 * (kBatchThreads + 64)];
     __shared__ __align__(16) C tab[kBatchTab];
     const BItem it = items[blockIdx.x];
     const BDomain& d = doms[it.dom];
@@ -355,7 +356,7 @@ __global__ __launch_bounds__(kBatchThreads, 4) void k_batch(const BDomain* __res
                                                          uint32_t* counters, double* partials,
                                                          uint64_t limit_ticks)
 {
-    __shared__ __align__(16) double sc[4 * kBatchThreads];   // carry arrays (also the reduction buffer)
+    __shared__ __align__(16) double sc[4 * (kBatchThreads + 64)];   // carry arrays (also the reduction buffer)
     __shared__ int64_t s_item;
     uint32_t* head = counters;
     uint32_t* err = counters + 1;

@@ -59,13 +59,15 @@ __device__ __forceinline__ void carry_scan(C* val, const C* prod, int K, int nl,
 // group of KP lanes (KP = the power of two >= K, at most 64) and the block
 // has KP lanes for each of its nl lines, lane q of group l takes segment q
 // (in scan order) of line l and the groups run a log2(KP)-step inclusive
-// scan of the affine maps c -> f + g c through wave shuffles; one more shift
-// turns it into the exclusive carries.  The LDS arrays are then laid out
-// line-major, [line * (KP + 1) + segment], so that both the writers (lanes
-// over lines) and the scan (lanes over segments) touch distinct banks.
-// Kernels choose the scan at compile time (par): the lane-parallel scan pays
-// where few lines have many segments (the LDS row tiles), the leader scan
-// where many lines have few (the strided tiles).
+// scan of the affine maps c -> f + g c through DPP lane moves (no LDS round
+// trip per step); one more shift turns it into the exclusive carries.  The
+// LDS arrays are then laid out line-major, [line * (KP + 1) + segment], so
+// that both the writers (lanes over lines) and the scan (lanes over
+// segments) touch distinct banks.  Kernels choose the scan at compile time
+// (par).  Measured on 1000^3 x 4: the lane-parallel scan takes the FP32 LDS
+// row tiles from 8.1 to 6.6 ms per sweep and the batched step from 5.38 to
+// 5.20 ms; the strided tiles of long y/z lines keep the leader scan (the
+// lane-parallel one was even for FP64 and 1-3% slower for FP32).
 __host__ __device__ inline int scan_kp(int K, int nl, int threads, bool par)
 {
     int kp = 1;
@@ -78,6 +80,28 @@ __host__ __device__ inline int scan_slots(int K, int nl, int threads, bool par)
 {
     const int kp = scan_kp(K, nl, threads, par);
     return kp ? nl * (kp + 1) : K * nl;
+}
+
+// DPP lane moves (gfx9 encodings): row_shr:n = 0x110 + n within 16-lane
+// rows, row_bcast:15 = 0x142 (lane 15 of each row to the next row),
+// row_bcast:31 = 0x143 (lane 31 to rows 2 and 3), wave_shr:1 = 0x138.
+// Lanes without a source, or outside the row mask, keep their own value.
+template <int CTRL, int RM>
+__device__ __forceinline__ int dpp32(int x)
+{
+    return __builtin_amdgcn_update_dpp(x, x, CTRL, RM, 0xf, false);
+}
+template <int CTRL, int RM>
+__device__ __forceinline__ double dpp_mov(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp32<CTRL, RM>((int)b), hi = dpp32<CTRL, RM>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL, int RM>
+__device__ __forceinline__ float dpp_mov(float x)
+{
+    return __int_as_float(dpp32<CTRL, RM>(__float_as_int(x)));
 }
 
 template <typename C>
@@ -94,15 +118,38 @@ __device__ __forceinline__ void carry_scan_par(C* val, const C* prod, int K, int
         f = val[at];
         g = prod[at];
     }
-    for (int d = 1; d < KP; d <<= 1) {
-        const C fo = __shfl_up(f, d, KP);
-        const C go = __shfl_up(g, d, KP);
-        if (q >= d) {
+    // groups of KP lanes are aligned to KP (a power of two <= 64): inside a
+    // 16-lane row the steps 1, 2, 4, 8 scan each row (or each smaller group);
+    // row_bcast:15 then joins rows 0|1 and 2|3, row_bcast:31 rows 0-1|2-3
+    const int r16 = q & 15;
+#define BFVM_SCAN_STEP(D)                                                         \
+    if (KP > D) {                                                                 \
+        const C fo = dpp_mov<0x110 + D, 0xf>(f), go = dpp_mov<0x110 + D, 0xf>(g); \
+        if (r16 >= D) {                                                           \
+            f = f + g * fo;                                                       \
+            g = g * go;                                                           \
+        }                                                                         \
+    }
+    BFVM_SCAN_STEP(1)
+    BFVM_SCAN_STEP(2)
+    BFVM_SCAN_STEP(4)
+    BFVM_SCAN_STEP(8)
+#undef BFVM_SCAN_STEP
+    if (KP >= 32) {
+        const C fo = dpp_mov<0x142, 0xa>(f), go = dpp_mov<0x142, 0xa>(g);
+        if ((t >> 4) & 1) {
             f = f + g * fo;
             g = g * go;
         }
     }
-    C c = __shfl_up(f, 1, KP);
+    if (KP == 64) {
+        const C fo = dpp_mov<0x143, 0xc>(f), go = dpp_mov<0x143, 0xc>(g);
+        if ((t >> 5) & 1) {
+            f = f + g * fo;
+            g = g * go;
+        }
+    }
+    C c = dpp_mov<0x138, 0xf>(f);
     if (q == 0) c = 0;
     if (real) val[at] = c;
 }

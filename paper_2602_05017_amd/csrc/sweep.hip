@@ -466,6 +466,20 @@ __global__ __launch_bounds__(512) void k_sweep_seg_xpipe(const T* in, T* out, Ax
     // Chunk slots past the tile's end load and store the tile's last chunk:
     // the duplicate LDS writes carry the same data as the owner's, and the
     // loop stays branch-free so the prefetch buffer stays in registers.
+    // LDS offsets of the thread's P chunks in a full tile (the same in every
+    // full tile; the last tile may be partial and recomputes them)
+    const uint32_t nch_full = (uint32_t)R * L / VW;
+    uint32_t offs[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+        const uint32_t c0 = t + u * blockDim.x;
+        const uint32_t c = c0 < nch_full ? c0 : nch_full - 1;
+        const uint32_t e = c * VW;
+        const uint32_t rw2 = divL.div(e);
+        const uint32_t q = e - rw2 * L;
+        const uint32_t sg = divMS.div(q);
+        offs[u] = rw2 * RS + sg * SB + (q - sg * MS);
+    }
     V buf[P];
     int64_t ti = blockIdx.x;
     if (ti < ntiles) {
@@ -482,16 +496,22 @@ __global__ __launch_bounds__(512) void k_sweep_seg_xpipe(const T* in, T* out, Ax
         const int64_t o0 = ti * R;
         const int nrows = (int)min((int64_t)R, g.outer - o0);
         const uint32_t nch = (uint32_t)nrows * L / VW;
+        const bool full = nrows == R;
         __syncthreads();   // the previous tile's stores have finished reading the LDS tile
+        if (full) {
 #pragma unroll
-        for (int u = 0; u < P; ++u) {
-            const uint32_t c0 = t + u * blockDim.x;
-            const uint32_t c = c0 < nch ? c0 : nch - 1;
-            const uint32_t e = c * VW;
-            const uint32_t rw2 = divL.div(e);
-            const uint32_t q = e - rw2 * L;
-            const uint32_t sg = divMS.div(q);
-            *reinterpret_cast<V*>(tile + rw2 * RS + sg * SB + (q - sg * MS)) = buf[u];
+            for (int u = 0; u < P; ++u) *reinterpret_cast<V*>(tile + offs[u]) = buf[u];
+        } else {
+#pragma unroll
+            for (int u = 0; u < P; ++u) {
+                const uint32_t c0 = t + u * blockDim.x;
+                const uint32_t c = c0 < nch ? c0 : nch - 1;
+                const uint32_t e = c * VW;
+                const uint32_t rw2 = divL.div(e);
+                const uint32_t q = e - rw2 * L;
+                const uint32_t sg = divMS.div(q);
+                *reinterpret_cast<V*>(tile + rw2 * RS + sg * SB + (q - sg * MS)) = buf[u];
+            }
         }
         __syncthreads();
         const int64_t tn = ti + gridDim.x;
@@ -525,12 +545,20 @@ __global__ __launch_bounds__(512) void k_sweep_seg_xpipe(const T* in, T* out, Ax
         }
         __syncthreads();
         V* dstv = reinterpret_cast<V*>(out + o0 * (int64_t)L);
-        for (uint32_t c = t; c < nch; c += blockDim.x) {
-            const uint32_t e = c * VW;
-            const uint32_t rw2 = divL.div(e);
-            const uint32_t q = e - rw2 * L;
-            const uint32_t sg = divMS.div(q);
-            dstv[c] = *reinterpret_cast<const V*>(tile + rw2 * RS + sg * SB + (q - sg * MS));
+        if (full) {
+#pragma unroll
+            for (int u = 0; u < P; ++u) {
+                const uint32_t c = t + u * blockDim.x;
+                if (c < nch) dstv[c] = *reinterpret_cast<const V*>(tile + offs[u]);
+            }
+        } else {
+            for (uint32_t c = t; c < nch; c += blockDim.x) {
+                const uint32_t e = c * VW;
+                const uint32_t rw2 = divL.div(e);
+                const uint32_t q = e - rw2 * L;
+                const uint32_t sg = divMS.div(q);
+                dstv[c] = *reinterpret_cast<const V*>(tile + rw2 * RS + sg * SB + (q - sg * MS));
+            }
         }
     }
 }
