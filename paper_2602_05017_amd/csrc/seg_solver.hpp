@@ -310,26 +310,16 @@ struct FastDiv {   // q / d for q * d <= 2^40: (q * m) >> 40
 // its own L2.  Giving XCD x the contiguous tile range
 // [x*per + min(x, rem), ...) instead makes neighbouring tiles - which share
 // cache lines and pages when a tile row is narrower than a 128-byte line -
-// run on the same XCD at about the same time.  With CH > 0 the XCDs take
-// chunks of CH tiles round-robin instead (XCD x gets the x-th chunk of every
-// 8 * CH tiles; the tail past the last whole round keeps launch order), so
-// the eight XCDs stream neighbouring regions together.  Both maps are
-// bijections of [0, gridDim.x * gridDim.y).
-template <uint32_t CH = 0>
+// run on the same XCD at about the same time.  The map is a bijection of
+// [0, gridDim.x * gridDim.y).
 __device__ __forceinline__ void xcd_tile(uint32_t& bx, uint32_t& by)
 {
     const uint32_t gx = gridDim.x;
     const uint32_t nb = gx * gridDim.y;
     const uint32_t L = blockIdx.y * gx + blockIdx.x;
     const uint32_t x = L % 8u, q = L / 8u;
-    uint32_t t;
-    if (CH == 0) {
-        const uint32_t per = nb / 8u, rem = nb % 8u;
-        t = x * per + (x < rem ? x : rem) + q;
-    } else {
-        const uint32_t full = nb / (8u * CH) * (8u * CH);
-        t = L < full ? (q / CH) * (8u * CH) + x * CH + (q % CH) : L;
-    }
+    const uint32_t per = nb / 8u, rem = nb % 8u;
+    const uint32_t t = x * per + (x < rem ? x : rem) + q;
     by = t / gx;
     bx = t - by * gx;
 }

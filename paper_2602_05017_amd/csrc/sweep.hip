@@ -205,10 +205,7 @@ __global__ __launch_bounds__(1024) void k_sweep_seg_strided(const T* in, T* out,
                                                             FastDiv divS, const C* __restrict__ comp, int H)
 {
     uint32_t bx, by;
-    // FP64 y tiles: chunks of 16 tiles round-robin over the XCDs measured 2%
-    // faster on 1000^3 x 4 (12.58 vs 12.86 ms); the x rows (3% slower), z and
-    // FP32 keep the contiguous ranges
-    xcd_tile<(sizeof(T) == 8 && AX == 1) ? 16u : 0u>(bx, by);
+    xcd_tile(bx, by);
     extern __shared__ __align__(16) unsigned char smem[];
     const int K = blockDim.x / lpw;
     C* sc = reinterpret_cast<C*>(smem);
