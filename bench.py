@@ -450,7 +450,7 @@ def run_endtoend(args):
         torch.cuda.synchronize()
         T["gaussian_profile"] = time.perf_counter() - t0
         t0 = time.perf_counter()                                             # (3) initial save
-        np.save(os.path.join(tmp, "initial.npy"), g.read_field(u))
+        g.save_npy(u, os.path.join(tmp, "initial.npy"))
         T["initial_save"] = time.perf_counter() - t0
         t0 = time.perf_counter()                                             # (4) agents
         g.set_sources(p.src.voxel, p.src.secretion, p.src.saturation, p.src.uptake)
@@ -461,7 +461,7 @@ def run_endtoend(args):
         torch.cuda.synchronize()
         T["simulate"] = time.perf_counter() - t0
         t0 = time.perf_counter()                                             # (6) final save
-        np.save(os.path.join(tmp, "final.npy"), g.read_field(u))
+        g.save_npy(u, os.path.join(tmp, "final.npy"))
         T["final_save"] = time.perf_counter() - t0
         g.close()
         del u

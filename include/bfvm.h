@@ -50,6 +50,7 @@ extern "C" {
 #define BFVM_EDEVICE (-4)   /* HIP runtime error; bfvm_last_error() has hipGetErrorString text */
 #define BFVM_ENOMEM  (-5)   /* host or device allocation failed */
 #define BFVM_EOFF    (-6)   /* the requested feature is switched off in this library version */
+#define BFVM_EIO     (-7)   /* a file could not be opened, read or written */
 
 /* ---- storage / arithmetic types ---------------------------------------- */
 #define BFVM_F64       0    /* double storage, double arithmetic, double coefficients */
@@ -160,6 +161,26 @@ int bfvm_fill_gaussian(bfvm_grid g, void* field, double cx, double cy, double cz
  * nx*ny*nz*nsub elements of the grid's storage type).  Synchronising.
  * Errors: EINVAL, EDEVICE. */
 int bfvm_read_field(bfvm_grid g, const void* field, void* host_dst);
+
+/* Field files.  The paper's end-to-end run writes its initial and final
+ * concentrations to files (Sec. 5.3, MATLAB format); these write and read
+ * NumPy .npy files instead: C order, shape (nz, ny, nx, nsub), element type
+ * '<f8' (BFVM_F64) or '<f4' (BFVM_F32, BFVM_F32_FAST), no conversion.
+ * The data moves in 32 MB chunks through two pinned host buffers that the
+ * grid allocates on first use (64 MB, freed by bfvm_destroy), so that the
+ * device copies on the grid's stream overlap the file I/O.
+ *
+ * bfvm_save_npy writes format version 1.0 after the work already enqueued on
+ * the grid's stream; it returns when the file is complete and closed.
+ * bfvm_load_npy reads format versions 1.0-3.0 into a device field of the
+ * grid; a file holding shape (nz, ny, nx) is accepted when nsub == 1.  It
+ * returns when the data is on the device (the grid's stream is synchronised).
+ * Errors: EINVAL (NULL pointers; not a .npy file; element type, order, shape
+ * or size that does not match the grid), EIO (open, read, write or close
+ * failed), ENOMEM, EDEVICE.  After an error the file or field contents are
+ * unspecified. */
+int bfvm_save_npy(bfvm_grid g, const void* field, const char* path);
+int bfvm_load_npy(bfvm_grid g, void* field, const char* path);
 
 /* Stage timing for measurement.  While enabled, every kernel launch of the
  * grid is bracketed by HIP events on the grid's stream.  Stages: 0 source,

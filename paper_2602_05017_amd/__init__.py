@@ -24,12 +24,13 @@ LIB_PATH = os.path.join(_HERE, "libbfvm.so")
 
 F64, F32, F32_FAST = 0, 1, 2
 DTYPES = {"f64": F64, "f32": F32, "f32fast": F32_FAST}
-STATUS = {0: "OK", -1: "EINVAL", -2: "ERANGE", -3: "ESTATE", -4: "EDEVICE", -5: "ENOMEM", -6: "EOFF"}
+STATUS = {0: "OK", -1: "EINVAL", -2: "ERANGE", -3: "ESTATE", -4: "EDEVICE", -5: "ENOMEM", -6: "EOFF", -7: "EIO"}
 
 # every entry point declared in include/bfvm.h
 EXPORTS = [
     "bfvm_create", "bfvm_destroy", "bfvm_set_stream", "bfvm_set_params", "bfvm_set_sources",
     "bfvm_set_dirichlet", "bfvm_step", "bfvm_sweep", "bfvm_step_adjoint", "bfvm_read_field",
+    "bfvm_save_npy", "bfvm_load_npy",
     "bfvm_fill_uniform", "bfvm_fill_gaussian", "bfvm_device_bytes",
     "bfvm_timing_enable", "bfvm_timing_read", "bfvm_timing_reset", "bfvm_timing_elements",
     "bfvm_set_schedule", "bfvm_get_schedule", "bfvm_get_plan", "bfvm_set_plan",
@@ -76,6 +77,8 @@ def lib():
     L.bfvm_sweep.argtypes = [_vp, _vp, _i32]
     L.bfvm_step_adjoint.argtypes = [_vp, _vp, _vp, _f64p, _f64p]
     L.bfvm_read_field.argtypes = [_vp, _vp, _vp]
+    L.bfvm_save_npy.argtypes = [_vp, _vp, ctypes.c_char_p]
+    L.bfvm_load_npy.argtypes = [_vp, _vp, ctypes.c_char_p]
     L.bfvm_timing_enable.argtypes = [_vp, _i32]
     L.bfvm_timing_read.argtypes = [_vp, _i32, _f64p, _i64p]
     L.bfvm_timing_reset.argtypes = [_vp]
@@ -262,6 +265,18 @@ class Grid:
         self._sync_stream()
         _check(lib().bfvm_read_field(self._handle, p, out.ctypes.data_as(_vp)), "bfvm_read_field")
         return out
+
+    def save_npy(self, field, path):
+        """Write a device field to a NumPy .npy file (shape (nz, ny, nx, nsub))."""
+        p = self._field_ptr(field)
+        self._sync_stream()
+        _check(lib().bfvm_save_npy(self._handle, p, os.fsencode(str(path))), "bfvm_save_npy")
+
+    def load_npy(self, field, path):
+        """Read a NumPy .npy file of this grid's shape and element type into a device field."""
+        p = self._field_ptr(field)
+        self._sync_stream()
+        _check(lib().bfvm_load_npy(self._handle, p, os.fsencode(str(path))), "bfvm_load_npy")
 
     # -------------------------------------------------------------- plans, timing
     def get_plan(self, axis: int):

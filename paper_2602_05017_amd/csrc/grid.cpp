@@ -386,6 +386,7 @@ const char* bfvm_status_string(int status)
         case BFVM_EDEVICE: return "HIP device error";
         case BFVM_ENOMEM: return "out of memory";
         case BFVM_EOFF: return "feature switched off";
+        case BFVM_EIO: return "file I/O error";
         default: return "unknown status";
     }
 }
@@ -453,6 +454,10 @@ int bfvm_destroy(bfvm_grid g)
         (void)hipEventDestroy(p.b);
     }
     for (auto e : g->ev_pool) (void)hipEventDestroy(e);
+    for (int b = 0; b < 2; ++b) {
+        if (g->io_buf[b]) (void)hipHostFree(g->io_buf[b]);
+        if (g->io_ev[b]) (void)hipEventDestroy(g->io_ev[b]);
+    }
     delete g;
     return BFVM_OK;
 }

@@ -164,6 +164,10 @@ struct bfvm_grid_s {
     int64_t red_blocks = 0;
     double* red_out = nullptr;
 
+    // pinned host buffers and events of the .npy field I/O (io.cpp)
+    void* io_buf[2] = {nullptr, nullptr};
+    hipEvent_t io_ev[2] = {nullptr, nullptr};
+
     // stage timing
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;

@@ -241,3 +241,35 @@ def test_batch_entry_points_validate_before_device_work(L):
     assert L.bfvm_batch_info(None, ctypes.byref(i64), ctypes.byref(i32), ctypes.byref(i64)) == -1
     assert L.bfvm_batch_destroy(None) == 0
     assert L.bfvm_status_string(-6) == b"feature switched off"
+
+
+def test_npy_io_rejects_files_that_do_not_match_the_grid(L, tmp_path):
+    # header checks run before any device work, so they are exercised here
+    st, g = _create(L, 6, 5, 4, 2)          # FP64 grid, shape (nz, ny, nx, S) = (4, 5, 6, 2)
+    assert st == 0
+    dev = ctypes.c_void_p(16)                # never dereferenced: every case fails before the copy
+
+    def load(path):
+        return L.bfvm_load_npy(g, dev, str(path).encode())
+
+    assert load(tmp_path / "missing.npy") == -7                               # EIO
+    (tmp_path / "junk.npy").write_bytes(b"not an array file at all")
+    assert load(tmp_path / "junk.npy") == -1
+    np.save(tmp_path / "f32.npy", np.zeros((4, 5, 6, 2), np.float32))
+    assert load(tmp_path / "f32.npy") == -1 and "element type" in bf.last_error()
+    np.save(tmp_path / "shape.npy", np.zeros((4, 5, 6, 3)))
+    assert load(tmp_path / "shape.npy") == -1 and "shape" in bf.last_error()
+    np.save(tmp_path / "flat.npy", np.zeros((4, 5, 6)))                       # 3-D only when nsub == 1
+    assert load(tmp_path / "flat.npy") == -1
+    np.save(tmp_path / "fortran.npy", np.asfortranarray(np.zeros((4, 5, 6, 2))))
+    assert load(tmp_path / "fortran.npy") == -1 and "Fortran" in bf.last_error()
+    np.save(tmp_path / "short.npy", np.zeros((4, 5, 6, 2)))
+    data = (tmp_path / "short.npy").read_bytes()
+    (tmp_path / "short.npy").write_bytes(data[:-8])                           # one element missing
+    assert load(tmp_path / "short.npy") == -1 and "size" in bf.last_error()
+    assert L.bfvm_load_npy(g, None, str(tmp_path / "short.npy").encode()) == -1
+    assert L.bfvm_load_npy(g, dev, None) == -1
+    assert L.bfvm_save_npy(g, None, str(tmp_path / "out.npy").encode()) == -1
+    assert L.bfvm_save_npy(g, dev, str(tmp_path / "no" / "such" / "dir.npy").encode()) == -7
+    assert L.bfvm_save_npy(None, dev, b"x.npy") == -1
+    L.bfvm_destroy(g)
