@@ -820,12 +820,16 @@ static hipError_t launch_seg(const SweepPlan& p, const AxisGeom& g, const T* in,
         const bool lds_tab = scan + tab <= (size_t)max_lds() && KMS < (1 << 24) && KMS * g.S <= (1ll << 40);
         // The exact compressed table replaces a full table that would not fit,
         // or that would take more than 48 KB of LDS (fewer workgroups per CU).
+        // It is also taken for FP32 storage and for the x rows, where the
+        // smaller per-block staging measured faster on 1000^3 x 4 (FP32 y 4%,
+        // z 3%, FP64 x rows 0.6%); FP64 y was even and FP64 z 4% slower.
         // compressed rows: head segments, constant, last slot's segment, zero;
         // usable when the head segments end before the last slot's segment
         const int nh = compH >= 0 ? (compH + M - 1) / M : 0;
         const bool comp_ok = comp && compH >= 0 && (g.n - 1) / M >= nh;
         const size_t ctab = comp_ok ? (size_t)g.S * (nh + 3) * (M + 1) * sizeof(C) : 0;
-        const bool use_comp = ctab > 0 && scan + ctab <= (size_t)max_lds() && (!lds_tab || tab > (48u << 10));
+        const bool use_comp = ctab > 0 && scan + ctab <= (size_t)max_lds() &&
+                              (!lds_tab || tab > (48u << 10) || sizeof(T) == 4 || xrows);
         const bool zaxis = g.axis == 2;
         const FastDiv dS((uint32_t)g.S);
         if (xrows && use_comp)
