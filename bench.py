@@ -13,7 +13,8 @@ agents, simulation, final save, each stage timed (fields saved as .npy).
 
 --workload liver12 / liver16: the larger Table 1 cubes on one GPU, 1500^3 x 8
 in FP64 (216 GB) and 2000^3 x 8 in FP32 (256 GB), fields written on the device
-(5 timed steps by default).
+(5 timed steps by default).  --workload liver4: Table 1's one-node case, 500^3 x 2
+in FP64 (50 timed steps), with the oracle on a bounded sample beside it.
 
 --workload adjoint: the differentiation workload, 128^3 x 2 substrates, 50
 steps with a checkpoint every 10, loss = sum of squared differences to a
@@ -61,7 +62,8 @@ def parse():
                     help="timed steps (default 20; 100 for the batch workload)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="liver",
-                    choices=["liver", "cells", "gaussian", "batch", "adjoint", "liver12", "liver16", "endtoend"])
+                    choices=["liver", "cells", "gaussian", "batch", "adjoint", "liver4", "liver12", "liver16",
+                             "endtoend"])
     ap.add_argument("--adjoint-steps", type=int, default=5,
                     help="batch workload: timed reverse steps of the 32-domain subset")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-storage companion run")
@@ -363,12 +365,23 @@ def run_adjoint(args):
     print(json.dumps(line), flush=True)
 
 
+# The paper's own step times for these cubes (Table 1, BioFVM-B, FP64 with
+# AVX256D on MareNostrum 5 nodes of 2 x Xeon Platinum 8480+): context for the
+# line, not a target of this measurement.
+PAPER_TABLE1 = {
+    "liver4": {"BioFVM-B_ms_per_step": 107.5, "nodes": 1, "BioFVM_ms": 241.4, "BioFVM-X_ms": 469},
+    "liver12": {"BioFVM-B_ms_per_step": 356.1, "nodes": 48},
+    "liver16": {"BioFVM-B_ms_per_step": 453.4, "nodes": 96, "note": "FP64 in the paper"},
+}
+
+
 def run_large(args):
     """A Table 1 cube that only fits on the device: the field is written there."""
     import torch
     import workloads
     p = workloads.large_config(args.workload)
-    steps = 5 if args.steps is None else args.steps
+    small = p.V * p.S <= 300_000_000          # fits the host: the oracle runs beside it
+    steps = (50 if small else 5) if args.steps is None else args.steps
     upd = p.V * p.S
     e = 8 if p.dtype == "f64" else 4
     log(f"workload {p.name}: {upd:.4g} voxel-substrates, field {upd * e / 1e9:.0f} GB, sources {len(p.src)}")
@@ -421,6 +434,13 @@ def run_large(args):
                    "bytes_per_voxel_substrate": round((upd * e + lib_bytes) / upd, 3)},
         "cpu_baseline": None,
     }
+    if args.workload in PAPER_TABLE1:
+        line["paper_context"] = PAPER_TABLE1[args.workload]
+    if small and not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample ...")
+        p.field()
+        line["cpu_baseline"] = cpu_baseline(p, args.cpu_sample_steps * 8)
+        log(f"oracle: {line['cpu_baseline']['value']:.4g} updates/s on {line['cpu_baseline']['cores']} threads")
     print(json.dumps(line), flush=True)
 
 
@@ -538,7 +558,7 @@ def main():
     if args.workload == "adjoint":
         run_adjoint(args)
         return
-    if args.workload in ("liver12", "liver16"):
+    if args.workload in ("liver4", "liver12", "liver16"):
         run_large(args)
         return
     if args.workload == "endtoend":

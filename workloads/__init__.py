@@ -297,6 +297,7 @@ def endtoend_config(nsteps: int = 500, with_field: bool = True) -> Problem:
 
 # Table 1 cases beyond the 1000^3 x 4 cube, at 10 um: (side, substrates, storage)
 LARGE_CASES = {
+    "liver4": (500, 2, "f64"),      # "4% liver": 500^3 x 2, 2 GB in FP64 (the paper's one-node case)
     "liver12": (1500, 8, "f64"),    # "12.5% liver": 1500^3 x 8, 216 GB in FP64
     "liver16": (2000, 8, "f32"),    # "16.6% liver": 2000^3 x 8, 256 GB in FP32 (512 GB in FP64)
 }
