@@ -224,6 +224,22 @@ int bfvm_get_schedule(bfvm_grid g, int32_t* schedule, int64_t* slab_width);
 int bfvm_get_plan(bfvm_grid g, int32_t axis, int32_t* kind, int32_t* m, int32_t* w, int32_t* lpw);
 int bfvm_set_plan(bfvm_grid g, int32_t axis, int32_t kind, int32_t m, int32_t w, int32_t lpw);
 
+/* Pick each axis's plan by measurement (a utility around the method, not
+ * part of it).  For every axis, the current plan and a candidate set are
+ * tried, and the fastest is kept:
+ *   - x: LDS row tiles and pipelined row tiles of 1-16 rows, and row lines
+ *     of 16 or 32 per tile;
+ *   - y, z: strided tiles of 16, 32 or 64 lines;
+ *   - each with 8, 16 or 32 elements per thread.
+ * A candidate is timed over `reps` sweeps (1..100) after one warm-up
+ * sweep, with HIP events on the grid's stream.  The sweeps run in place
+ * on `field`, a device field of the grid: its contents are overwritten
+ * (each sweep is a contraction, so values stay bounded).  best_ms (host
+ * [3], may be NULL) receives each axis's time per sweep.  Synchronising.
+ * Errors: EINVAL (NULL pointers, reps), ESTATE (before set_params),
+ * EDEVICE. */
+int bfvm_autotune(bfvm_grid g, void* field, int32_t reps, float* best_ms);
+
 /* ---- batched domains -------------------------------------------------- */
 /*
  * Many independent grids (uneven sizes and substrate counts, any mix of

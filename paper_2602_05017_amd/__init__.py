@@ -33,7 +33,7 @@ EXPORTS = [
     "bfvm_save_npy", "bfvm_load_npy",
     "bfvm_fill_uniform", "bfvm_fill_gaussian", "bfvm_device_bytes",
     "bfvm_timing_enable", "bfvm_timing_read", "bfvm_timing_reset", "bfvm_timing_elements",
-    "bfvm_set_schedule", "bfvm_get_schedule", "bfvm_get_plan", "bfvm_set_plan",
+    "bfvm_set_schedule", "bfvm_get_schedule", "bfvm_get_plan", "bfvm_set_plan", "bfvm_autotune",
     "bfvm_batch_create", "bfvm_batch_destroy", "bfvm_batch_set_mode", "bfvm_batch_set_fields", "bfvm_batch_step",
     "bfvm_batch_step_eager", "bfvm_batch_step_adjoint", "bfvm_batch_autotune", "bfvm_batch_get_plan",
     "bfvm_batch_info",
@@ -87,6 +87,7 @@ def lib():
     L.bfvm_get_schedule.argtypes = [_vp, _i32p, _i64p]
     L.bfvm_get_plan.argtypes = [_vp, _i32, _i32p, _i32p, _i32p, _i32p]
     L.bfvm_set_plan.argtypes = [_vp, _i32, _i32, _i32, _i32, _i32]
+    L.bfvm_autotune.argtypes = [_vp, _vp, _i32, ctypes.POINTER(ctypes.c_float)]
     L.bfvm_batch_create.argtypes = [ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]
     L.bfvm_batch_destroy.argtypes = [_vp]
     L.bfvm_batch_set_fields.argtypes = [_vp, _i32, ctypes.POINTER(_vp)]
@@ -286,6 +287,15 @@ class Grid:
 
     def set_plan(self, axis: int, kind: int, m: int = 0, w: int = 0, lpw: int = 0):
         _check(lib().bfvm_set_plan(self._handle, axis, kind, m, w, lpw), "bfvm_set_plan")
+
+    def autotune(self, field, reps: int = 3):
+        """Time candidate plans on `field` (overwritten) and keep the fastest per axis.
+        Returns ([plan per axis], [ms per sweep per axis])."""
+        p = self._field_ptr(field)
+        self._sync_stream()
+        ms = (ctypes.c_float * 3)()
+        _check(lib().bfvm_autotune(self._handle, p, reps, ms), "bfvm_autotune")
+        return [self.get_plan(a) for a in range(3)], [float(x) for x in ms]
 
     def set_schedule(self, schedule: int, slab_width: int = 0):
         _check(lib().bfvm_set_schedule(self._handle, schedule, slab_width), "bfvm_set_schedule")

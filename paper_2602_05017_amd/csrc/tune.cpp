@@ -1,0 +1,121 @@
+// Plan autotuning for one grid.  A measurement utility around the method,
+// not part of it: every valid plan of a candidate set is timed on the
+// caller's field with HIP events on the grid's stream, and each axis keeps
+// its fastest plan.  The candidates span the kernels of every plan kind:
+// LDS row tiles (plain and pipelined) and row lines for x, strided tiles of
+// 16, 32 or 64 lines for y and z, each with 8, 16 or 32 elements per
+// thread and as few segments as cover the line.
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace {
+
+int tune_fail(int code, const std::string& msg)
+{
+    bfvm::set_error(msg);
+    return code;
+}
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+std::vector<bfvm::SweepPlan> candidates(int axis, const bfvm::AxisGeom& g)
+{
+    std::vector<bfvm::SweepPlan> out;
+    auto add = [&](int kind, int m, int64_t w, int64_t lpw) {
+        bfvm::SweepPlan p;
+        p.kind = kind;
+        p.m = m;
+        p.w = (int)w;
+        p.lpw = (int)lpw;
+        out.push_back(p);
+    };
+    if (axis == 0) {
+        for (int M : {8, 16, 32}) {
+            const int64_t per_row = cdiv(g.n, M) * g.S;
+            for (int64_t R : {1, 2, 4, 8, 16}) {
+                if (per_row * R > 512) break;
+                const int64_t w = cdiv(per_row * R, 64);
+                add(bfvm::PLAN_SEG_XTILE, M, w, R);
+                if (M != 32) add(bfvm::PLAN_SEG_XPIPE, M, w, R);
+            }
+        }
+        for (int M : {8, 16, 32})
+            for (int lpw : {16, 32}) {
+                const int spw = 64 / lpw;
+                const int64_t K = cdiv(cdiv(g.n, M), spw) * spw;
+                if (K * lpw / 64 <= 16) add(bfvm::PLAN_SEG_XROWS, M, K * lpw / 64, lpw);
+            }
+    } else {
+        for (int M : {8, 16, 32})
+            for (int lpw : {16, 32, 64}) {
+                const int spw = 64 / lpw;
+                const int64_t K = cdiv(cdiv(g.n, M), spw) * spw;
+                if (K * lpw / 64 <= 16) add(bfvm::PLAN_SEG_STRIDED, M, K * lpw / 64, lpw);
+            }
+    }
+    return out;
+}
+
+struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+}  // namespace
+
+int bfvm_autotune(bfvm_grid g, void* field, int32_t reps, float* best_ms)
+{
+    if (!g) return tune_fail(BFVM_EINVAL, "grid is NULL");
+    if (!field) return tune_fail(BFVM_EINVAL, "field is NULL");
+    if (reps < 1 || reps > 100) return tune_fail(BFVM_EINVAL, "reps must be in [1, 100]");
+    if (!g->have_params) return tune_fail(BFVM_ESTATE, "set_params must come before autotune");
+    Events ev;
+    if (hipEventCreate(&ev.a) != hipSuccess || hipEventCreate(&ev.b) != hipSuccess)
+        return tune_fail(BFVM_EDEVICE, "hipEventCreate");
+    for (int axis = 0; axis < 3; ++axis) {
+        const bfvm::AxisGeom geo = bfvm::axis_geom(axis, g->nx, g->ny, g->nz, g->S);
+        const bfvm::SweepPlan keep = g->plan[axis];
+        std::vector<bfvm::SweepPlan> cand = candidates(axis, geo);
+        cand.insert(cand.begin(), keep);
+        bfvm::SweepPlan best = keep;
+        float best_t = 0.0f;
+        bool have = false;
+        for (const bfvm::SweepPlan& c : cand) {
+            if (!bfvm::check_plan(c, geo, g->dtype).empty()) continue;
+            g->plan[axis] = c;
+            int st = bfvm_sweep(g, field, axis);   // warm-up (and the first use of the kernel)
+            if (st) {
+                g->plan[axis] = keep;
+                return st;
+            }
+            if (hipEventRecord(ev.a, g->stream) != hipSuccess) return tune_fail(BFVM_EDEVICE, "hipEventRecord");
+            for (int r = 0; r < reps && !st; ++r) st = bfvm_sweep(g, field, axis);
+            if (st) {
+                g->plan[axis] = keep;
+                return st;
+            }
+            float ms = 0.0f;
+            if (hipEventRecord(ev.b, g->stream) != hipSuccess || hipEventSynchronize(ev.b) != hipSuccess ||
+                hipEventElapsedTime(&ms, ev.a, ev.b) != hipSuccess) {
+                g->plan[axis] = keep;
+                return tune_fail(BFVM_EDEVICE, "event timing");
+            }
+            ms /= (float)reps;
+            if (!have || ms < best_t) {
+                best = c;
+                best_t = ms;
+                have = true;
+            }
+        }
+        g->plan[axis] = best;
+        if (best_ms) best_ms[axis] = best_t;
+    }
+    return BFVM_OK;
+}

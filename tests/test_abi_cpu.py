@@ -273,3 +273,15 @@ def test_npy_io_rejects_files_that_do_not_match_the_grid(L, tmp_path):
     assert L.bfvm_save_npy(g, dev, str(tmp_path / "no" / "such" / "dir.npy").encode()) == -7
     assert L.bfvm_save_npy(None, dev, b"x.npy") == -1
     L.bfvm_destroy(g)
+
+
+def test_autotune_validates_before_any_device_work(L):
+    st, g = _create(L, 20, 10, 8, 2)
+    assert st == 0
+    dev = ctypes.c_void_p(16)
+    assert L.bfvm_autotune(None, dev, 3, None) == -1
+    assert L.bfvm_autotune(g, None, 3, None) == -1
+    assert L.bfvm_autotune(g, dev, 0, None) == -1          # reps out of range
+    assert L.bfvm_autotune(g, dev, 101, None) == -1
+    assert L.bfvm_autotune(g, dev, 3, None) == -3          # ESTATE: no parameters yet
+    L.bfvm_destroy(g)

@@ -311,3 +311,24 @@ def test_cells_full_workload_100_steps():
     flat = got.reshape(-1, p.S)
     act = p.dr.active.astype(bool)
     assert np.array_equal(flat[p.dr.voxel[act[:, 0]], 0], p.dr.value[act[:, 0], 0])
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", F64_TOL), ("f32", F32_TOL)])
+def test_autotuned_plans_are_valid_and_keep_parity(dtype, tol):
+    import torch
+    p = small_problem((150, 70, 90), 3, seed=820, nsrc=200, ndir=20, nsteps=4)
+    g = make_grid(p, dtype)
+    scratch = torch.empty(p.shape, dtype=g.torch_dtype, device="cuda")
+    g.fill_uniform(scratch, 3, 0)
+    plans, ms = g.autotune(scratch, reps=2)
+    assert all(t > 0 for t in ms)
+    for axis, plan in enumerate(plans):
+        g.set_plan(axis, *plan)                  # read back, accepted as is
+    u = upload(p, g)
+    g.step(u, p.nsteps)
+    torch.cuda.synchronize()
+    got = g.read_field(u)
+    g.close()
+    emax, _ = rel_err(got, oracle_run(p))
+    print(f"autotuned {dtype} plans {plans} ({['%.3f' % t for t in ms]} ms): e_max {emax:.3e}")
+    assert emax <= tol
