@@ -455,7 +455,10 @@ def run_endtoend(args):
     steps = p.nsteps if args.steps is None else args.steps
     tmp = tempfile.mkdtemp(prefix="bfvm_e2e_")
 
-    def pipeline(nsteps):
+    def pipeline(nsteps, out):
+        # each pass writes new files into its own folder: truncating the
+        # previous pass's files would add the file system's truncate cost
+        os.makedirs(out)
         T = {}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -470,7 +473,7 @@ def run_endtoend(args):
         torch.cuda.synchronize()
         T["gaussian_profile"] = time.perf_counter() - t0
         t0 = time.perf_counter()                                             # (3) initial save
-        g.save_npy(u, os.path.join(tmp, "initial.npy"))
+        g.save_npy(u, os.path.join(out, "initial.npy"))
         T["initial_save"] = time.perf_counter() - t0
         t0 = time.perf_counter()                                             # (4) agents
         g.set_sources(p.src.voxel, p.src.secretion, p.src.saturation, p.src.uptake)
@@ -481,7 +484,7 @@ def run_endtoend(args):
         torch.cuda.synchronize()
         T["simulate"] = time.perf_counter() - t0
         t0 = time.perf_counter()                                             # (6) final save
-        g.save_npy(u, os.path.join(tmp, "final.npy"))
+        g.save_npy(u, os.path.join(out, "final.npy"))
         T["final_save"] = time.perf_counter() - t0
         g.close()
         del u
@@ -489,8 +492,8 @@ def run_endtoend(args):
         return T
 
     try:
-        pipeline(2)                      # warm-up: library, kernels, file system
-        T = pipeline(steps)
+        pipeline(2, os.path.join(tmp, "warmup"))     # warm-up: library, kernels, file system
+        T = pipeline(steps, os.path.join(tmp, "run"))
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
     total = sum(T.values())
