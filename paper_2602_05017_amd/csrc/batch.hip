@@ -258,10 +258,15 @@ __device__ void batch_sparse_item(const BDomain& d, const BItem& it, double* par
             const SweepShape q = sweep_shape(d, it.axis);
             const int64_t vstride = it.axis == 0 ? 1 : (it.axis == 1 ? d.nx : d.nx * d.ny);
             const int64_t est = vstride * S;
+            // (v / vstride) % n through FP64 reciprocals: (w + 1/2) / d lies at
+            // least 1/(2d) from an integer and errs by less than 2^-20 / d for
+            // w < 2^31, so truncation is exact
+            const double inv_vs = 1.0 / (double)vstride, inv_n = 1.0 / (double)q.n;
             for (int s = 0; s < S; ++s) {
                 double a0 = 0.0, a1 = 0.0;
                 for (int64_t v = it.a0 + threadIdx.x; v < it.a1; v += blockDim.x) {
-                    const int64_t i = (v / vstride) % q.n;
+                    const int64_t qv = (int64_t)(((double)v + 0.5) * inv_vs);
+                    const int64_t i = qv - (int64_t)(((double)qv + 0.5) * inv_n) * q.n;
                     const int64_t e = v * S + s;
                     const double xe = (double)x[e];
                     double lx = 0.0;

@@ -649,10 +649,11 @@ int bfvm_step_adjoint(bfvm_grid g, const void* field_in, void* grad, double* gra
             }
         }
     }
+    // partials of the three axes side by side, summed by one final launch
     const int64_t nb = adjoint_reduce_blocks(g->nvox());
     if (!g->red_partials || g->red_blocks < nb) {
         dfree(g->red_partials);
-        HIP_TRY(hipMalloc((void**)&g->red_partials, sizeof(double) * 2 * S * nb), "hipMalloc partials");
+        HIP_TRY(hipMalloc((void**)&g->red_partials, sizeof(double) * 3 * 2 * S * nb), "hipMalloc partials");
         g->red_blocks = nb;
     }
     if (!g->red_out) HIP_TRY(hipMalloc((void**)&g->red_out, sizeof(double) * 2 * S * 3), "hipMalloc red_out");
@@ -681,10 +682,12 @@ int bfvm_step_adjoint(bfvm_grid g, const void* field_in, void* grad, double* gra
         if (e != hipSuccess) return hip_fail(e, "mask kernel");
         if ((rc = run_sweep(g, a, grad, grad, true))) return rc;
         const AxisGeom geo = axis_geom(a, g->nx, g->ny, g->nz, S);
-        e = launch_adjoint_reduce(g->dtype, grad, g->work[a], geo, g->nelem(), g->red_partials, g->red_blocks,
-                                  g->red_out + 2 * S * a, st);
+        e = launch_adjoint_partials(g->dtype, grad, g->work[a], geo, g->nelem(), g->red_partials + a * 2 * S * nb,
+                                    nb, st);
         if (e != hipSuccess) return hip_fail(e, "adjoint reduction");
     }
+    hipError_t ef = launch_adjoint_final(g->red_partials, nb, S, 3, g->red_out, st);
+    if (ef != hipSuccess) return hip_fail(ef, "adjoint reduction");
     hipError_t e = launch_mask(g->dtype, grad, g->dir_elem, g->ndir, st);
     if (e != hipSuccess) return hip_fail(e, "mask kernel");
     e = launch_source_transpose(g->dtype, grad, g->src_vox, g->src_invQ, g->nsrc, S, st);
