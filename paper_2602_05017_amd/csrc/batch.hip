@@ -262,6 +262,48 @@ __device__ void batch_sparse_item(const BDomain& d, const BItem& it, double* par
             // least 1/(2d) from an integer and errs by less than 2^-20 / d for
             // w < 2^31, so truncation is exact
             const double inv_vs = 1.0 / (double)vstride, inv_n = 1.0 / (double)q.n;
+            if (2 * S <= (int)blockDim.x) {
+                // One pass over the item's elements for all substrates: thread t
+                // takes the elements t, t + L, t + 2L, ... of [a0 S, a1 S) with
+                // L = S * P, P = blockDim / S rows of S threads, so its substrate
+                // t % S never changes (threads from L on idle).  Then one
+                // fixed-order tree over the P rows: deterministic.
+                const int t = threadIdx.x, P = (int)blockDim.x / S, L = P * S;
+                const int sub = t % S, row = t / S;
+                double a0 = 0.0, a1 = 0.0;
+                if (t < L) {
+                    for (int64_t v = it.a0 + row; v < it.a1; v += P) {
+                        const int64_t qv = (int64_t)(((double)v + 0.5) * inv_vs);
+                        const int64_t i = qv - (int64_t)(((double)qv + 0.5) * inv_n) * q.n;
+                        const int64_t e = v * S + sub;
+                        const double xe = (double)x[e];
+                        double lx = 0.0;
+                        if (i > 0) lx += xe - (double)x[e - est];
+                        if (i < q.n - 1) lx += xe - (double)x[e + est];
+                        const double ye = (double)y[e];
+                        a0 += ye * lx;
+                        a1 += ye * xe;
+                    }
+                }
+                red[t] = a0;
+                red[blockDim.x + t] = a1;
+                __syncthreads();
+                int w0 = 1;
+                while (w0 < P) w0 <<= 1;
+                for (int w = w0 / 2; w > 0; w >>= 1) {
+                    if (t < L && row < w && row + w < P) {
+                        red[t] += red[t + w * S];
+                        red[blockDim.x + t] += red[blockDim.x + t + w * S];
+                    }
+                    __syncthreads();
+                }
+                if (t < S) {
+                    partials[it.slot + 2 * t + 0] = red[t];
+                    partials[it.slot + 2 * t + 1] = red[blockDim.x + t];
+                }
+                __syncthreads();
+                break;
+            }
             for (int s = 0; s < S; ++s) {
                 double a0 = 0.0, a1 = 0.0;
                 for (int64_t v = it.a0 + threadIdx.x; v < it.a1; v += blockDim.x) {
