@@ -198,8 +198,12 @@ int bfvm_load_npy(bfvm_grid g, void* field, const char* path)
     for (size_t i = 0; i < nchunk; ++i) {
         const size_t off = i * kIoChunk, len = std::min(kIoChunk, total - off);
         if (i >= 2) IO_HIP(hipEventSynchronize(g->io_ev[i % 2]), "hipEventSynchronize");
-        if (std::fread(g->io_buf[i % 2], 1, len, f.f) != len)
+        if (std::fread(g->io_buf[i % 2], 1, len, f.f) != len) {
+            // copies still in flight read the pinned buffers that the next
+            // call refills from the host
+            (void)hipStreamSynchronize(g->stream);
             return io_fail(BFVM_EIO, std::string("read failed: ") + path);
+        }
         IO_HIP(hipMemcpyAsync(dst + off, g->io_buf[i % 2], len, hipMemcpyHostToDevice, g->stream),
                "hipMemcpyAsync");
         IO_HIP(hipEventRecord(g->io_ev[i % 2], g->stream), "hipEventRecord");
