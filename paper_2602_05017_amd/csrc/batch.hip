@@ -348,10 +348,14 @@ __device__ void batch_sparse_item(const BDomain& d, const BItem& it, double* par
 // once per item, so the tiles read their coefficients from LDS instead of
 // issuing as many global loads as they load field values.
 
-// M <= 8: at most 128 VGPRs, so that two 512-thread blocks fit per CU
+// At most 128 VGPRs (four waves per SIMD), so that two 512-thread blocks
+// fit per CU, except the transposed M = 16 tiles.  Measured on 96 uneven
+// domains: the forward M = 16 tiles at 128 VGPRs (a few spilled) instead of
+// 136 took the step from 5.21 to 4.78 ms; the transposed ones (45 spilled)
+// made the reverse step 8% slower, so they keep one block per CU.
 template <typename T, typename C, int M, bool TR>
-__global__ __launch_bounds__(kBatchThreads, M <= 8 ? 4 : 2) void k_group_sweep(const BDomain* __restrict__ doms,
-                                                                               const BItem* __restrict__ items)
+__global__ __launch_bounds__(kBatchThreads, (TR && M > 8) ? 2 : 4) void k_group_sweep(const BDomain* __restrict__ doms,
+                                                                                      const BItem* __restrict__ items)
 {
     // carry arrays, lane-parallel layout: lpw * (K + 1) = 512 + lpw <= 576 slots each
     __shared__ __align__(16) C sc[4 * (kBatchThreads + 64)];
