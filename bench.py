@@ -275,11 +275,11 @@ def run_batch(args):
     print(json.dumps(line), flush=True)
 
 
-# algorithmic bytes per element of one reverse step without Dirichlet
-# entries, in units of the element size: copy of the state (2), three
-# recomputed sweeps (6), three transposed sweeps (6), three reductions
-# reading the gradient and the sweep output (6)
-ADJOINT_ELEMS_MOVED = 20
+# algorithmic bytes per element of one reverse step without sources and
+# Dirichlet entries, in units of the element size: three recomputed sweeps
+# (6, the first reading the state itself), three transposed sweeps (6),
+# three reductions reading the gradient and the sweep output (6)
+ADJOINT_ELEMS_MOVED = 18
 
 
 def run_adjoint(args):

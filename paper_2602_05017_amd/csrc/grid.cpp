@@ -662,11 +662,17 @@ int bfvm_step_adjoint(bfvm_grid g, const void* field_in, void* grad, double* gra
     // forward recomputation: work[a] = output of sweep a (before the following
     // Dirichlet overwrite).  Without Dirichlet entries sweep a reads work[a-1]
     // directly; with them it runs on an overwritten copy, so that work[a-1]
-    // keeps the sweep output the reduction needs.
-    HIP_TRY(hipMemcpyAsync(g->work[0], field_in, bytes, hipMemcpyDeviceToDevice, st), "copy");
-    if ((rc = run_source(g, g->work[0]))) return rc;
-    if ((rc = run_dirichlet(g, g->work[0]))) return rc;
-    if ((rc = run_sweep(g, 0, g->work[0], g->work[0], false))) return rc;
+    // keeps the sweep output the reduction needs.  Without sources either,
+    // nothing changes the state before the x sweep, which then reads field_in
+    // itself instead of a copy.
+    if (g->nsrc == 0 && g->ndir == 0) {
+        if ((rc = run_sweep(g, 0, field_in, g->work[0], false))) return rc;
+    } else {
+        HIP_TRY(hipMemcpyAsync(g->work[0], field_in, bytes, hipMemcpyDeviceToDevice, st), "copy");
+        if ((rc = run_source(g, g->work[0]))) return rc;
+        if ((rc = run_dirichlet(g, g->work[0]))) return rc;
+        if ((rc = run_sweep(g, 0, g->work[0], g->work[0], false))) return rc;
+    }
     for (int a = 1; a < 3; ++a) {
         if (g->ndir > 0) {
             HIP_TRY(hipMemcpyAsync(g->work[a], g->work[a - 1], bytes, hipMemcpyDeviceToDevice, st), "copy");
