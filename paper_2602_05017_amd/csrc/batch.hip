@@ -624,8 +624,12 @@ void build_program(bfvm_batch b, const std::vector<int32_t>& which, const std::v
                 case ST_DIR: case ST_MASK: total = d.ndir; chunk = b->chunk_elems; break;
                 // a domain without Dirichlet entries needs no copy between the
                 // recomputed sweeps: its y and z sweeps read the previous
-                // sweep's buffer and write their own (out of place, below)
-                case ST_COPY: total = (sg.in != 0 && d.ndir == 0) ? 0 : nel; chunk = b->chunk_elems; break;
+                // sweep's buffer and write their own (out of place, below);
+                // without sources either, its x sweep reads the state itself
+                case ST_COPY:
+                    total = (d.ndir == 0 && (sg.in != 0 || d.nsrc == 0)) ? 0 : nel;
+                    chunk = b->chunk_elems;
+                    break;
                 case ST_REDUCE: total = d.nx * d.ny * d.nz; chunk = std::max<int64_t>(1, b->chunk_elems / d.S); break;
                 default: {
                     total = tiles_of(d, sg.axis);
@@ -640,7 +644,10 @@ void build_program(bfvm_batch b, const std::vector<int32_t>& which, const std::v
                 it.axis = sg.axis;
                 it.in = sg.in;
                 it.out = sg.out;
-                if (sg.type == ST_SWEEP && sg.in == sg.out && sg.in >= 3 && d.ndir == 0) it.in = sg.in - 1;
+                if (sg.type == ST_SWEEP && sg.in == sg.out && sg.in >= 2 && d.ndir == 0) {
+                    if (sg.in >= 3) it.in = sg.in - 1;
+                    else if (d.nsrc == 0) it.in = 0;
+                }
                 it.a0 = a0;
                 it.a1 = std::min(total, a0 + chunk);
                 if (sg.type == ST_REDUCE) {
@@ -712,7 +719,8 @@ std::vector<Stage> forward_program()
 // Written for domains with Dirichlet entries (each sweep runs on an
 // overwritten copy, so the previous sweep's output stays intact for its
 // reduction); build_program drops the two inner copies of a domain without
-// Dirichlet entries and runs its y and z sweeps 2 -> 3 and 3 -> 4.
+// Dirichlet entries and runs its y and z sweeps 2 -> 3 and 3 -> 4; without
+// sources either, it also drops the first copy and runs the x sweep 0 -> 2.
 std::vector<Stage> adjoint_program()
 {
     return {{ST_COPY, 0, 0, 2},    {ST_SRC, 0, 2, 2},     {ST_DIR, 0, 2, 2},   {ST_SWEEP, 0, 2, 2},

@@ -129,8 +129,14 @@ def test_batch_adjoint_subset_matches_single_grid_adjoint(mode):
     import torch
     import paper_2602_05017_amd as bf
     probs = _domains(9, lo=24, hi=64, nsteps=1, seed=1008)
+    # subset domains: 2 with Dirichlet entries (every copy kept), 0 and 8 with
+    # sources only (inner copies dropped), 5 with neither (no copy: the x
+    # sweep reads the state itself)
     probs[2].dr = workloads.dirichlet_variant(probs[2], 7)
+    probs[5].src = None
+    assert all(probs[i].src is not None for i in (0, 2, 8)) and probs[5].dr is None
     grids, fields = _setup(probs)
+    state = [f.clone() for f in fields]
     rng = np.random.default_rng(9)
     grads = [torch.from_numpy(rng.random(p.shape) - 0.5).to(device="cuda", dtype=g.torch_dtype)
              for p, g in zip(probs, grids)]
@@ -139,6 +145,8 @@ def test_batch_adjoint_subset_matches_single_grid_adjoint(mode):
     b.set_grads(grads)
     subset = [0, 2, 5, 8]
     gD, gL = b.step_adjoint(subset)
+    torch.cuda.synchronize()
+    assert all(torch.equal(f, f0) for f, f0 in zip(fields, state))   # states are only read
     off = 0
     for i in subset:
         p, g = probs[i], grids[i]
