@@ -674,7 +674,7 @@ std::string check_plan(const SweepPlan& p, const AxisGeom& g, int dtype)
 SweepPlan default_plan(int axis, const AxisGeom& g, int dtype)
 {
     SweepPlan p;
-    const int es = (int)dtype_size(dtype);
+    const int es = (int)dtype_size(dtype), cs = compute_size(dtype);
     if (axis == 0) {
         // One or two substrates per row: the strided row kernel would read
         // pieces of 8-16 bytes of each row per instruction, so rows go
@@ -713,12 +713,18 @@ SweepPlan default_plan(int axis, const AxisGeom& g, int dtype)
         // FP32 storage on long rows: the strided kernel's loads would touch
         // 16-byte pieces of each row per instruction, so rows go through LDS
         // with coalesced 16-byte loads, in the pipelined row-tile kernel
+        // (FP32 arithmetic, from 512 voxels: two rows per tile where they fit
+        // 512 threads; 6.77 -> 6.36 ms on 1000^3 x 4)
         if (es == 4 && g.n >= 256) {
             SweepPlan c;
             c.kind = PLAN_SEG_XPIPE;
             c.m = 16;
+            const int64_t per_row = ceil_div(g.n, 16) * g.S;
+            c.lpw = (cs == 4 && g.n >= 512 && 2 * per_row <= 512) ? 2 : 1;
+            c.w = (int)ceil_div(c.lpw * per_row, 64);
+            if (check_plan(c, g, dtype).empty()) return c;
             c.lpw = 1;
-            c.w = (int)ceil_div(ceil_div(g.n, 16) * g.S, 64);
+            c.w = (int)ceil_div(per_row, 64);
             if (check_plan(c, g, dtype).empty()) return c;
         }
         // preferred: every (row, substrate) as a line of the strided kernel;
@@ -763,9 +769,11 @@ SweepPlan default_plan(int axis, const AxisGeom& g, int dtype)
         return p;   // kind 0
     }
     // FP32 y lines on long axes: 32-line tiles (a full 128-byte line per
-    // row) measured 2-3% faster than 16-line tiles on 1000^3 x 4; FP32 z and
-    // FP64 lines keep 16-line tiles (z was 15% slower with 32)
-    if (es == 4 && axis == 1 && g.n >= 512) {
+    // row) measured 2-3% faster than 16-line tiles on 1000^3 x 4; FP32 z
+    // with FP64 arithmetic and FP64 lines keep 16-line tiles (z was 15%
+    // slower with 32).  With FP32 arithmetic (half the registers) z takes
+    // 32-line tiles too: 7.66 -> 7.00 ms on 1000^3 x 4.
+    if (es == 4 && (axis == 1 || cs == 4) && g.n >= 512) {
         SweepPlan c;
         c.kind = PLAN_SEG_STRIDED;
         c.m = 32;
