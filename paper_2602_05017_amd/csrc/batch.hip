@@ -52,6 +52,7 @@ enum StageType : int32_t {
 };
 
 constexpr int kBatchThreads = 512;
+constexpr int64_t kSparseChunk = 2048;   // source / Dirichlet entries per item
 constexpr int kBatchTab = 2048;   // line length x substrates, per axis
 // elements per thread M in {4, 8} and at most 512/16 = 32 segments per line
 constexpr int64_t kMaxBatchLine = 256;
@@ -217,10 +218,11 @@ __device__ void batch_sparse_item(const BDomain& d, const BItem& it, double* par
     const int S = d.S;
     switch (it.type) {
         case ST_SRC: {
+            // entry indices are below nsrc * S <= the domain's elements < 2^31
             T* u = static_cast<T*>(d.buf[it.out]);
             for (int64_t t = it.a0 + threadIdx.x; t < it.a1; t += blockDim.x) {
-                const int64_t k = t / S;
-                const int64_t e = d.src_vox[k] * S + (t - k * S);
+                const uint32_t k = (uint32_t)t / (uint32_t)S;
+                const int64_t e = d.src_vox[k] * S + ((uint32_t)t - k * (uint32_t)S);
                 u[e] = (T)(((double)u[e] + d.src_P[t]) * d.src_invQ[t]);
             }
             break;
@@ -228,8 +230,8 @@ __device__ void batch_sparse_item(const BDomain& d, const BItem& it, double* par
         case ST_SRC_T: {
             T* g = static_cast<T*>(d.buf[it.out]);
             for (int64_t t = it.a0 + threadIdx.x; t < it.a1; t += blockDim.x) {
-                const int64_t k = t / S;
-                const int64_t e = d.src_vox[k] * S + (t - k * S);
+                const uint32_t k = (uint32_t)t / (uint32_t)S;
+                const int64_t e = d.src_vox[k] * S + ((uint32_t)t - k * (uint32_t)S);
                 g[e] = (T)((double)g[e] * d.src_invQ[t]);
             }
             break;
@@ -620,8 +622,10 @@ void build_program(bfvm_batch b, const std::vector<int32_t>& which, const std::v
             const int64_t nel = d.nx * d.ny * d.nz * d.S;
             int64_t total = 0, chunk = 1;
             switch (sg.type) {
-                case ST_SRC: case ST_SRC_T: total = d.nsrc * d.S; chunk = b->chunk_elems; break;
-                case ST_DIR: case ST_MASK: total = d.ndir; chunk = b->chunk_elems; break;
+                // scattered sparse entries: small items, so that a launch has
+                // blocks for every CU and each thread few dependent accesses
+                case ST_SRC: case ST_SRC_T: total = d.nsrc * d.S; chunk = kSparseChunk; break;
+                case ST_DIR: case ST_MASK: total = d.ndir; chunk = kSparseChunk; break;
                 // a domain without Dirichlet entries needs no copy between the
                 // recomputed sweeps: its y and z sweeps read the previous
                 // sweep's buffer and write their own (out of place, below);
