@@ -315,6 +315,16 @@ int bfvm_batch_autotune(bfvm_batch b, const char* cache_path, double* best_ms);
 
 /* Elements per thread (m) and lines per tile (lpw) of a domain's axis. */
 int bfvm_batch_get_plan(bfvm_batch b, int32_t domain, int32_t axis, int32_t* m, int32_t* lpw);
+
+/* Set a domain axis's plan by hand (the autotuner's choice otherwise):
+ * m in {4, 8, 16} (8 at most in persistent mode), lpw in {16, 32, 64},
+ * and the 512 / lpw segments of m elements must cover the line.  Rebuilds
+ * the forward program; the next reverse step rebuilds its own.  The
+ * transposed sweeps of an M = 16 axis run as M = 8 with half the lines per
+ * tile (at least 16) where those still cover the line.  Errors: EINVAL
+ * (NULL batch, unsupported or too small plan), ERANGE (domain or axis),
+ * EDEVICE. */
+int bfvm_batch_set_plan(bfvm_batch b, int32_t domain, int32_t axis, int32_t m, int32_t lpw);
 /* Work items of one forward step, kernel launches per step, work per item. */
 int bfvm_batch_info(bfvm_batch b, int64_t* items, int32_t* launches, int64_t* chunk_elems);
 

@@ -36,6 +36,7 @@ EXPORTS = [
     "bfvm_set_schedule", "bfvm_get_schedule", "bfvm_get_plan", "bfvm_set_plan", "bfvm_autotune",
     "bfvm_batch_create", "bfvm_batch_destroy", "bfvm_batch_set_mode", "bfvm_batch_set_fields", "bfvm_batch_step",
     "bfvm_batch_step_eager", "bfvm_batch_step_adjoint", "bfvm_batch_autotune", "bfvm_batch_get_plan",
+    "bfvm_batch_set_plan",
     "bfvm_batch_info",
     "bfvm_status_string", "bfvm_last_error", "bfvm_version",
 ]
@@ -96,6 +97,7 @@ def lib():
     L.bfvm_batch_step_adjoint.argtypes = [_vp, _i32, _i32p, _f64p, _f64p]
     L.bfvm_batch_autotune.argtypes = [_vp, ctypes.c_char_p, _f64p]
     L.bfvm_batch_get_plan.argtypes = [_vp, _i32, _i32, _i32p, _i32p]
+    L.bfvm_batch_set_plan.argtypes = [_vp, _i32, _i32, _i32, _i32]
     L.bfvm_batch_info.argtypes = [_vp, _i64p, _i32p, _i64p]
     L.bfvm_status_string.argtypes = [ctypes.c_int]
     L.bfvm_status_string.restype = ctypes.c_char_p
@@ -416,6 +418,9 @@ class Batch:
         _check(lib().bfvm_batch_get_plan(self._handle, domain, axis, ctypes.byref(m), ctypes.byref(l)),
                "bfvm_batch_get_plan")
         return m.value, l.value
+
+    def set_plan(self, domain: int, axis: int, m: int, lpw: int):
+        _check(lib().bfvm_batch_set_plan(self._handle, domain, axis, m, lpw), "bfvm_batch_set_plan")
 
     def info(self):
         it, bl, ch = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()

@@ -84,6 +84,7 @@ struct BItem {
     int32_t done;      // counter incremented when the item completes
     int32_t dep;       // counter to wait for (-1: none)
     uint32_t need;     // value of counter dep that means "stage complete"
+    int32_t m, lpw;    // sweeps: elements per thread and lines per tile
     int64_t a0, a1;    // range (tiles, entries, elements or voxels)
     int64_t slot;      // REDUCE: offset of the item's 2*S partial sums
 };
@@ -197,7 +198,7 @@ template <typename T, typename C, bool TR>
 __device__ void batch_sweep_item(const BDomain& d, const BItem& it, C* sc)
 {
     const SweepShape q = sweep_shape(d, it.axis);
-    const int lpw = d.lpw[it.axis];
+    const int lpw = it.lpw;
     const int64_t tpo = (q.inner + lpw - 1) / lpw;   // tiles per outer index
     const T* in = static_cast<const T*>(d.buf[it.in]);
     T* out = static_cast<T*>(d.buf[it.out]);
@@ -205,7 +206,7 @@ __device__ void batch_sweep_item(const BDomain& d, const BItem& it, C* sc)
     const C* rr = static_cast<const C*>(d.r[it.axis]);
     for (int64_t t = it.a0; t < it.a1; ++t) {
         const int64_t oy = t / tpo, ox = t - oy * tpo;
-        if (d.M[it.axis] == 4)
+        if (it.m == 4)
             batch_tile<T, C, 4, TR>(in, out, q, d.S, lpw, ox, oy, invd, rr, sc);
         else
             batch_tile<T, C, 8, TR>(in, out, q, d.S, lpw, ox, oy, invd, rr, sc);
@@ -365,7 +366,7 @@ __global__ __launch_bounds__(kBatchThreads, (TR && M > 8) ? 2 : 4) void k_group_
     const BItem it = items[blockIdx.x];
     const BDomain& d = doms[it.dom];
     const SweepShape q = sweep_shape(d, it.axis);
-    const int lpw = d.lpw[it.axis];
+    const int lpw = it.lpw;
     const int64_t tpo = (q.inner + lpw - 1) / lpw;   // tiles per outer index
     const T* in = static_cast<const T*>(d.buf[it.in]);
     T* out = static_cast<T*>(d.buf[it.out]);
@@ -562,13 +563,13 @@ struct bfvm_batch_s {
 
 namespace {
 
-int64_t tiles_of(const BDomain& d, int axis)
+int64_t tiles_of(const BDomain& d, int axis, int lpw)
 {
     int64_t inner, outer;
     if (axis == 0) { inner = d.ny * d.nz * d.S; outer = 1; }
     else if (axis == 1) { inner = d.nx * d.S; outer = d.nz; }
     else { inner = d.nx * d.ny * d.S; outer = 1; }
-    return (inner + d.lpw[axis] - 1) / d.lpw[axis] * outer;
+    return (inner + lpw - 1) / lpw * outer;
 }
 
 int64_t axis_len(const BDomain& d, int axis) { return axis == 0 ? d.nx : (axis == 1 ? d.ny : d.nz); }
@@ -586,6 +587,23 @@ int smallest_m(int64_t n, int lpw, int max_m)
 }
 
 int max_m_for_mode(int mode) { return mode == BFVM_BATCH_PERSISTENT ? 8 : 16; }
+
+// Tile shape of a sweep stage: the domain's plan, except that a transposed
+// sweep of M = 16 runs as M = 8 with half the lines per tile (at least 16)
+// where those segments still cover the line.  The transposed M = 16 tiles
+// need 170 VGPRs, one 512-thread block per CU; at M = 8 (115) two fit.
+void tile_shape(const BDomain& d, int axis, bool transposed, int* m, int* lpw)
+{
+    *m = d.M[axis];
+    *lpw = d.lpw[axis];
+    if (transposed && *m == 16) {
+        const int l = std::max(16, *lpw / 2);
+        if (plan_fits(axis_len(d, axis), 8, l)) {
+            *m = 8;
+            *lpw = l;
+        }
+    }
+}
 
 // default per-axis plan: the most lines per tile (widest coalesced rows)
 // whose segments of at most 8 elements still cover the line (16 only if
@@ -621,6 +639,8 @@ void build_program(bfvm_batch b, const std::vector<int32_t>& which, const std::v
             const BDomain& d = b->doms[which[wi]];
             const int64_t nel = d.nx * d.ny * d.nz * d.S;
             int64_t total = 0, chunk = 1;
+            int tm = 0, tl = 0;
+            if (sg.type == ST_SWEEP || sg.type == ST_SWEEP_T) tile_shape(d, sg.axis, sg.type == ST_SWEEP_T, &tm, &tl);
             switch (sg.type) {
                 // scattered sparse entries: small items, so that a launch has
                 // blocks for every CU and each thread few dependent accesses
@@ -636,8 +656,8 @@ void build_program(bfvm_batch b, const std::vector<int32_t>& which, const std::v
                     break;
                 case ST_REDUCE: total = d.nx * d.ny * d.nz; chunk = std::max<int64_t>(1, b->chunk_elems / d.S); break;
                 default: {
-                    total = tiles_of(d, sg.axis);
-                    const int64_t per_tile = (int64_t)d.lpw[sg.axis] * axis_len(d, sg.axis);
+                    total = tiles_of(d, sg.axis, tl);
+                    const int64_t per_tile = (int64_t)tl * axis_len(d, sg.axis);
                     chunk = std::max<int64_t>(1, b->chunk_elems / std::max<int64_t>(per_tile, 1));
                 }
             }
@@ -648,6 +668,8 @@ void build_program(bfvm_batch b, const std::vector<int32_t>& which, const std::v
                 it.axis = sg.axis;
                 it.in = sg.in;
                 it.out = sg.out;
+                it.m = tm;
+                it.lpw = tl;
                 if (sg.type == ST_SWEEP && sg.in == sg.out && sg.in >= 2 && d.ndir == 0) {
                     if (sg.in >= 3) it.in = sg.in - 1;
                     else if (d.nsrc == 0) it.in = 0;
@@ -688,7 +710,7 @@ void build_program(bfvm_batch b, const std::vector<int32_t>& which, const std::v
         for (size_t wi = 0; wi < which.size(); ++wi) {
             if (per[wi][k].empty()) continue;
             const BDomain& d = b->doms[which[wi]];
-            const std::pair<int, int> c{d.dtype, sweep ? d.M[sg.axis] : 0};
+            const std::pair<int, int> c{d.dtype, sweep ? per[wi][k].front().m : 0};
             if (std::find(classes.begin(), classes.end(), c) == classes.end()) classes.push_back(c);
         }
         for (const auto& c : classes) {
@@ -700,7 +722,8 @@ void build_program(bfvm_batch b, const std::vector<int32_t>& which, const std::v
             L.off = (int64_t)P.items.size();
             for (size_t wi = 0; wi < which.size(); ++wi) {
                 const BDomain& d = b->doms[which[wi]];
-                if (sweep && (d.dtype != c.first || d.M[sg.axis] != c.second)) continue;
+                if (per[wi][k].empty()) continue;
+                if (sweep && (d.dtype != c.first || per[wi][k].front().m != c.second)) continue;
                 if (!sweep && d.dtype != c.first) continue;
                 for (auto& it : per[wi][k]) P.items.push_back(it);
             }
@@ -1160,6 +1183,22 @@ int bfvm_batch_get_plan(bfvm_batch b, int32_t domain, int32_t axis, int32_t* m, 
     *m = b->doms[domain].M[axis];
     *lpw = b->doms[domain].lpw[axis];
     return BFVM_OK;
+}
+
+int bfvm_batch_set_plan(bfvm_batch b, int32_t domain, int32_t axis, int32_t m, int32_t lpw)
+{
+    if (!b) return bfail(BFVM_EINVAL, "batch is NULL");
+    if (domain < 0 || domain >= (int32_t)b->doms.size() || axis < 0 || axis > 2)
+        return bfail(BFVM_ERANGE, "domain or axis");
+    if (m != 4 && m != 8 && m != 16) return bfail(BFVM_EINVAL, "m must be 4, 8 or 16");
+    if (m > max_m_for_mode(b->mode)) return bfail(BFVM_EINVAL, "m too large for the batch mode");
+    if (lpw != 16 && lpw != 32 && lpw != 64) return bfail(BFVM_EINVAL, "lpw must be 16, 32 or 64");
+    BDomain& d = b->doms[domain];
+    if (!plan_fits(axis_len(d, axis), m, lpw)) return bfail(BFVM_EINVAL, "too few segments for the line length");
+    d.M[axis] = m;
+    d.lpw[axis] = lpw;
+    if (int st = upload_doms(b)) return st;
+    return build_forward(b);
 }
 
 int bfvm_batch_info(bfvm_batch b, int64_t* items, int32_t* launches, int64_t* chunk_elems)

@@ -142,6 +142,12 @@ def test_batch_adjoint_subset_matches_single_grid_adjoint(mode):
              for p, g in zip(probs, grids)]
     gin = [x.clone() for x in grads]
     b = bf.Batch(grids, fields, mode=mode)
+    before = b.plan(1, 1)
+    # M = 16 axes in the subset: their transposed sweeps run as M = 8 tiles of
+    # half the lines (64 -> 32, 32 -> 16, 16 -> 16)
+    for dom, axis, plan in ((0, 1, (16, 64)), (2, 2, (16, 32)), (5, 0, (16, 16)), (8, 1, (16, 64))):
+        b.set_plan(dom, axis, *plan)
+        assert b.plan(dom, axis) == plan
     b.set_grads(grads)
     subset = [0, 2, 5, 8]
     gD, gL = b.step_adjoint(subset)
@@ -164,6 +170,14 @@ def test_batch_adjoint_subset_matches_single_grid_adjoint(mode):
     # a second call on the same subset replays the captured graph
     gD2, gL2 = b.step_adjoint(subset)
     assert np.all(np.isfinite(gD2)) and np.all(np.isfinite(gL2))
+    # plans that do not fit are refused, and the domain keeps its plan
+    for dom, axis, m, lpw, code in ((1, 1, 4, 64, "EINVAL"),     # 8 segments x 4 < 63
+                                    (1, 1, 5, 16, "EINVAL"), (1, 1, 8, 128, "EINVAL"),
+                                    (1, 3, 8, 16, "ERANGE"), (9, 0, 8, 16, "ERANGE")):
+        with pytest.raises(bf.BfvmError) as ei:
+            b.set_plan(dom, axis, m, lpw)
+        assert ei.value.code == code
+    assert b.plan(1, 1) == before
     b.close()
 
 
