@@ -94,6 +94,34 @@ def test_batch_equals_single_grid_steps(mode):
         assert rel_err(out, ref)[0] <= TOL[p.dtype], p.name
 
 
+def test_batch_hand_set_plans_match_oracle():
+    # every (M, lines per tile) shape the autotuner may choose, fixed by hand
+    # on both storage types, against the oracle: M = 16 tiles are held to
+    # 128 VGPRs (a few spilled) and reached otherwise only by tuning
+    import paper_2602_05017_amd as bf
+    probs = _domains(6, lo=24, hi=120, nsteps=2, seed=1012)
+    probs[3].dr = workloads.dirichlet_variant(probs[3], 5)
+    grids, fields = _setup(probs)
+    b = bf.Batch(grids, fields)
+    shapes = [(16, 16), (16, 32), (16, 64), (8, 16), (8, 32), (8, 64), (4, 16), (4, 32), (4, 64)]
+    set_any = {"f64": 0, "f32": 0}
+    for d, p in enumerate(probs):
+        for a, n in enumerate((p.nx, p.ny, p.nz)):
+            fits = [(m, l) for m, l in shapes if (512 // l) * m >= n]
+            m, l = fits[(3 * d + a) % len(fits)]
+            b.set_plan(d, a, m, l)
+            assert b.plan(d, a) == (m, l)
+            set_any[p.dtype] += m == 16
+    assert set_any["f64"] and set_any["f32"]
+    b.step(2)
+    for p, g, f in zip(probs, grids, fields):
+        u = np.array(p.u0, copy=True)
+        src, dr = oracle_lists(p)
+        oracle.step(u, p.h, p.D, p.lam, p.dt, src, dr, 2)
+        assert rel_err(g.read_field(f), u)[0] <= TOL[p.dtype], p.name
+    b.close()
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_autotuner_picks_valid_plans_and_keeps_results(tmp_path, mode):
     import torch
