@@ -82,6 +82,34 @@ def test_adjoint_step_matches_oracle(shape, S, nsrc, ndir):
     assert np.max(np.abs(gL - rL) / np.abs(rL)) <= 1e-12
 
 
+def test_adjoint_step_fp32_arithmetic_matches_oracle():
+    # FP32 storage and arithmetic, constants rounded to FP32: the oracle's
+    # FP64 adjoint of the FP32-rounded state and gradient, within the FP32
+    # form's 1e-5 (dL/dD, a sum of neighbour differences, within 1e-4);
+    # measured 2.4e-7, 5.4e-6 (dL/dD) and 4.9e-7 (dL/dlambda)
+    import torch
+    p = small_problem((21, 17, 13), 3, seed=801, nsrc=40, ndir=6)
+    rng = np.random.default_rng(4)
+    gin = (rng.random(p.shape) - 0.5).astype(np.float32)
+    g = make_grid(p, "f32fast")
+    u = upload(p, g)
+    gg = torch.from_numpy(gin.copy()).cuda()
+    gD, gL = g.step_adjoint(u, gg)
+    torch.cuda.synchronize()
+    got = gg.double().cpu().numpy()
+    g.close()
+    src, dr = oracle_lists(p)
+    ref = gin.astype(np.float64)
+    rD = np.zeros(p.S)
+    rL = np.zeros(p.S)
+    oracle.adjoint_step(p.u0.astype(np.float32).astype(np.float64), ref, rD, rL, p.h, p.D, p.lam, p.dt, src, dr)
+    e = rel_err(got, ref)[0]
+    eD = np.max(np.abs(gD - rD) / np.abs(rD))
+    eL = np.max(np.abs(gL - rL) / np.abs(rL))
+    print(f"f32fast adjoint step: grad e_max {e:.2e}, dD {eD:.2e}, dlambda {eL:.2e}")
+    assert e <= 1e-5 and eL <= 1e-5 and eD <= 1e-4
+
+
 @pytest.mark.parametrize("K", [1, 3, 10])
 def test_autograd_matches_oracle_gradient(K):
     p = small_problem((24, 19, 22), 2, seed=810, nsrc=60, ndir=10, nsteps=7)

@@ -122,6 +122,43 @@ def test_batch_hand_set_plans_match_oracle():
     b.close()
 
 
+def test_batch_with_fp32_arithmetic_domains():
+    # three storage types, so three launch chains (batch stream and two side
+    # streams); FP32-arithmetic domains against the oracle at their bar, and
+    # their reverse step against the single-grid one
+    import torch
+    import paper_2602_05017_amd as bf
+    probs = _domains(6, lo=24, hi=80, nsteps=2, seed=1013)
+    for k in (1, 4):
+        probs[k].dtype = "f32fast"
+    assert {p.dtype for p in probs} == {"f64", "f32", "f32fast"}
+    grids, fields = _setup(probs)
+    b = bf.Batch(grids, fields)
+    b.step(2)
+    for p, g, f in zip(probs, grids, fields):
+        u = np.array(p.u0, copy=True)
+        src, dr = oracle_lists(p)
+        oracle.step(u, p.h, p.D, p.lam, p.dt, src, dr, 2)
+        assert rel_err(g.read_field(f), u)[0] <= TOL[p.dtype], p.name
+    rng = np.random.default_rng(13)
+    grads = [torch.from_numpy(rng.random(p.shape) - 0.5).to(device="cuda", dtype=g.torch_dtype)
+             for p, g in zip(probs, grids)]
+    gin = [x.clone() for x in grads]
+    b.set_grads(grads)
+    subset = [1, 2, 4]
+    gD, gL = b.step_adjoint(subset)
+    off = 0
+    for i in subset:
+        p, g = probs[i], grids[i]
+        ref_g = gin[i].clone()
+        rD, rL = g.step_adjoint(fields[i], ref_g)
+        tol = TOL[p.dtype]
+        assert rel_err(grads[i].double().cpu().numpy(), ref_g.double().cpu().numpy())[0] <= tol, p.name
+        assert np.max(np.abs(gL[off:off + p.S] - rL) / np.abs(rL)) <= max(tol, 1e-11), p.name
+        off += p.S
+    b.close()
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_autotuner_picks_valid_plans_and_keeps_results(tmp_path, mode):
     import torch
