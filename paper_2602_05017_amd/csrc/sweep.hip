@@ -713,14 +713,15 @@ SweepPlan default_plan(int axis, const AxisGeom& g, int dtype)
         // FP32 storage on long rows: the strided kernel's loads would touch
         // 16-byte pieces of each row per instruction, so rows go through LDS
         // with coalesced 16-byte loads, in the pipelined row-tile kernel
-        // (FP32 arithmetic, from 512 voxels: two rows per tile where they fit
-        // 512 threads; 6.77 -> 6.36 ms on 1000^3 x 4)
+        // (from 512 voxels: two rows per tile where they fit 512 threads; on
+        // 1000^3 x 4, FP32 arithmetic 6.77 -> 6.36 ms, FP64 arithmetic 6.63
+        // -> 6.52 ms in alternating runs)
         if (es == 4 && g.n >= 256) {
             SweepPlan c;
             c.kind = PLAN_SEG_XPIPE;
             c.m = 16;
             const int64_t per_row = ceil_div(g.n, 16) * g.S;
-            c.lpw = (cs == 4 && g.n >= 512 && 2 * per_row <= 512) ? 2 : 1;
+            c.lpw = (g.n >= 512 && 2 * per_row <= 512) ? 2 : 1;
             c.w = (int)ceil_div(c.lpw * per_row, 64);
             if (check_plan(c, g, dtype).empty()) return c;
             c.lpw = 1;
