@@ -25,7 +25,9 @@ class LODSteps(torch.autograd.Function):
     @staticmethod
     def forward(ctx, u0, D, lam, grid: Grid, dt: float, nsteps: int, checkpoint_every: int):
         K = max(1, int(checkpoint_every))
-        grid.set_params(D.detach().cpu().double().numpy(), lam.detach().cpu().double().numpy(), dt)
+        Dn = D.detach().cpu().double().numpy().copy()
+        Ln = lam.detach().cpu().double().numpy().copy()
+        grid.set_params(Dn, Ln, dt)
         u = u0.detach().to(grid.torch_dtype).contiguous().clone()
         ckpts = []
         for t in range(nsteps):
@@ -33,6 +35,9 @@ class LODSteps(torch.autograd.Function):
                 ckpts.append(u.clone())
             grid.step(u, 1)
         ctx.grid = grid
+        # the grid may run other forward passes (with other parameters)
+        # before this backward: backward re-installs these
+        ctx.params = (Dn, Ln, float(dt))
         ctx.nsteps = nsteps
         ctx.K = K
         ctx.in_dtype = u0.dtype
@@ -42,6 +47,7 @@ class LODSteps(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gout):
         grid = ctx.grid
+        grid.set_params(*ctx.params)
         N, K = ctx.nsteps, ctx.K
         ckpts = ctx.saved_tensors
         g = gout.detach().to(grid.torch_dtype).contiguous().clone()

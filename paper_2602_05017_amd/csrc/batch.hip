@@ -539,6 +539,7 @@ void free_program(Program& P)
 
 struct bfvm_batch_s {
     std::vector<bfvm_grid> grids;
+    std::vector<uint64_t> gens;       // each grid's setter count when its descriptor was last read
     std::vector<BDomain> doms;        // host copy of the descriptors
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -948,8 +949,24 @@ int refresh_from_grids(bfvm_batch b)
         d.dir_elem = g->dir_elem;
         d.dir_val = g->dir_val;
         d.ndir = g->ndir;
+        b->gens[i] = g->gen;
     }
     return BFVM_OK;
+}
+
+// A member grid's setters free and reallocate its coefficient tables and
+// source / Dirichlet lists (and may change their lengths), which the device
+// descriptors and the captured programs point to.  Before every call that
+// runs work, re-read any grid whose setter count moved, then rebuild the
+// programs; the graphs are captured again on their next run.
+int sync_grids(bfvm_batch b)
+{
+    bool moved = false;
+    for (size_t i = 0; i < b->grids.size(); ++i) moved |= b->grids[i]->gen != b->gens[i];
+    if (!moved) return BFVM_OK;
+    refresh_from_grids(b);
+    if (int st = upload_doms(b)) return st;
+    return build_forward(b);
 }
 
 }  // namespace
@@ -997,6 +1014,7 @@ int bfvm_batch_create(bfvm_batch* out, int32_t ndomains, const bfvm_grid* grids,
         return bfail(BFVM_EDEVICE, "fork event creation");
     }
     b->grids.assign(grids, grids + ndomains);
+    b->gens.assign(ndomains, 0);
     b->doms.resize(ndomains);
     std::memset(b->doms.data(), 0, sizeof(BDomain) * ndomains);
     refresh_from_grids(b);
@@ -1079,6 +1097,7 @@ int bfvm_batch_step(bfvm_batch b, int64_t nsteps)
     if (!b) return bfail(BFVM_EINVAL, "batch is NULL");
     if (nsteps < 0) return bfail(BFVM_EINVAL, "nsteps must be >= 0");
     if (nsteps == 0) return BFVM_OK;
+    if (int st = sync_grids(b)) return st;
     if (!b->fwd.exec)
         if (int st = capture(b, b->fwd)) return st;
     for (int64_t t = 0; t < nsteps; ++t) BHIP(hipGraphLaunch(b->fwd.exec, b->stream), "graph launch");
@@ -1089,6 +1108,7 @@ int bfvm_batch_step_eager(bfvm_batch b, int64_t nsteps)
 {
     if (!b) return bfail(BFVM_EINVAL, "batch is NULL");
     if (nsteps < 0) return bfail(BFVM_EINVAL, "nsteps must be >= 0");
+    if (int st = sync_grids(b)) return st;
     for (int64_t t = 0; t < nsteps; ++t)
         if (int st = enqueue_program(b, b->fwd)) return st;
     return finish(b);
@@ -1104,6 +1124,7 @@ int bfvm_batch_step_adjoint(bfvm_batch b, int32_t count, const int32_t* subset, 
         for (int32_t j = 0; j < i; ++j)
             if (subset[j] == subset[i]) return bfail(BFVM_EINVAL, "repeated domain in subset");
     }
+    if (int st = sync_grids(b)) return st;
     std::vector<int32_t> sub(subset, subset + count);
     if (sub != b->adj_subset || !b->adj.exec) {
         // (re)build the adjoint program: workspace, items, partials, graph
@@ -1195,6 +1216,7 @@ int bfvm_batch_set_plan(bfvm_batch b, int32_t domain, int32_t axis, int32_t m, i
     if (lpw != 16 && lpw != 32 && lpw != 64) return bfail(BFVM_EINVAL, "lpw must be 16, 32 or 64");
     BDomain& d = b->doms[domain];
     if (!plan_fits(axis_len(d, axis), m, lpw)) return bfail(BFVM_EINVAL, "too few segments for the line length");
+    if (int st = sync_grids(b)) return st;
     d.M[axis] = m;
     d.lpw[axis] = lpw;
     if (int st = upload_doms(b)) return st;
@@ -1310,6 +1332,7 @@ bool plan_ok(int mode, int64_t n, int m, int lpw)
 extern "C" int bfvm_batch_autotune(bfvm_batch b, const char* cache_path, double* best_ms)
 {
     if (!b || !best_ms) return bfail(BFVM_EINVAL, "NULL");
+    if (int st = sync_grids(b)) return st;
     int dev = 0;
     (void)hipGetDevice(&dev);
     hipDeviceProp_t prop;

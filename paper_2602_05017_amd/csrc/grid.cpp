@@ -508,6 +508,7 @@ int bfvm_set_params(bfvm_grid g, const double* D, const double* lambda, double d
         }
         comp32[a].assign(comp[a].begin(), comp[a].end());
     }
+    ++g->gen;
     for (int a = 0; a < 3; ++a) {
         int st;
         if ((st = dalloc_copy(g->invd64[a], invd[a].data(), invd[a].size(), g->stream))) return st;
@@ -542,6 +543,7 @@ int bfvm_set_sources(bfvm_grid g, int64_t count, const int64_t* voxel, const dou
     if (count > 0 && (!finite_nonneg(secretion, count * S) || !finite_nonneg(saturation, count * S) ||
                       !finite_nonneg(uptake, count * S)))
         return fail(BFVM_EINVAL, "source rates must be finite and >= 0");
+    ++g->gen;
     g->raw_vox.assign(voxel, voxel + count);
     g->raw_sec.assign(secretion, secretion + count * S);
     g->raw_sat.assign(saturation, saturation + count * S);
@@ -584,6 +586,7 @@ int bfvm_set_dirichlet(bfvm_grid g, int64_t count, const int64_t* voxel, const d
         elem.push_back(ent[i].first);
         val.push_back(value[ent[i].second]);
     }
+    ++g->gen;
     int st;
     if ((st = dalloc_copy(g->dir_elem, elem.data(), elem.size(), g->stream))) return st;
     if ((st = dalloc_copy(g->dir_val, val.data(), val.size(), g->stream))) return st;

@@ -117,6 +117,10 @@ struct bfvm_grid_s {
 
     bool have_params = false;
     double dt = 0.0;
+    // bumped by every setter that may reallocate the device tables or lists
+    // below (set_params, set_sources, set_dirichlet); a batch holding this
+    // grid compares it before each call and re-reads the grid when it moved
+    uint64_t gen = 0;
     std::vector<double> D, lambda;
 
     // coefficient tables per axis (device): double and float copies

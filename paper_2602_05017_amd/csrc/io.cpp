@@ -143,8 +143,12 @@ int bfvm_save_npy(bfvm_grid g, const void* field, const char* path)
         if (i > 0) {
             const size_t j = i - 1, off = j * kIoChunk, len = std::min(kIoChunk, total - off);
             IO_HIP(hipEventSynchronize(g->io_ev[j % 2]), "hipEventSynchronize");
-            if (std::fwrite(g->io_buf[j % 2], 1, len, f.f) != len)
+            if (std::fwrite(g->io_buf[j % 2], 1, len, f.f) != len) {
+                // the copy of chunk i may still be filling the other pinned
+                // buffer, which the next save or load on this grid reuses
+                (void)hipStreamSynchronize(g->stream);
                 return io_fail(BFVM_EIO, std::string("write failed: ") + path);
+            }
         }
     }
     const int closed = std::fclose(f.f);
