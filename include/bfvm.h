@@ -109,6 +109,9 @@ int bfvm_set_dirichlet(bfvm_grid g, int64_t count, const int64_t* voxel,
 
 /* Advance the device field by nsteps LOD steps, in place:
  *   Src, Dir, X, Dir, Y, Dir, Z, Dir   (per step).
+ * This is the diffusion-decay solver of Sec. 2: the seven stages (four
+ * Dirichlet applications interleaved with the x, y and z Thomas solves of
+ * Algorithm 1), preceded by the cells' bulk source/sink update of Sec. 5.3.
  * Asynchronous on the grid's stream; allocates nothing.
  * Errors: EINVAL (field NULL, nsteps < 0), ESTATE (no params), EDEVICE. */
 int bfvm_step(bfvm_grid g, void* field, int64_t nsteps);
@@ -158,7 +161,10 @@ int bfvm_fill_gaussian(bfvm_grid g, void* field, double cx, double cy, double cz
                        double noise, uint64_t seed, uint32_t stream);
 
 /* Copy a device field of this grid to host memory (host_dst holds
- * nx*ny*nz*nsub elements of the grid's storage type).  Synchronising.
+ * nx*ny*nz*nsub elements of the grid's storage type), the read-back behind
+ * the end-to-end run's saving of the concentrations (Sec. 5.3).  host_dst
+ * is caller-owned (pageable or pinned).  Synchronising: returns after the
+ * work enqueued on the grid's stream and the copy have finished.
  * Errors: EINVAL, EDEVICE. */
 int bfvm_read_field(bfvm_grid g, const void* field, void* host_dst);
 
@@ -240,6 +246,27 @@ int bfvm_set_plan(bfvm_grid g, int32_t axis, int32_t kind, int32_t m, int32_t w,
  * EDEVICE. */
 int bfvm_autotune(bfvm_grid g, void* field, int32_t reps, float* best_ms);
 
+/* Device memory for a field of this grid, with its placement chosen by
+ * measurement (a utility around the method, like bfvm_autotune).  The rate
+ * of the sweeps on a field depends on where its allocation lands in device
+ * memory; so `candidates` allocations of the field's size are made side by
+ * side (fewer if they would leave less than max(1/16 of the device, 4 GB)
+ * free), each is filled with bounded values and timed on one x, y and z
+ * sweep set (after one untimed set) with HIP events on the grid's stream,
+ * and the fastest is kept; the others are freed before the call returns.
+ * *field receives the kept allocation (nx*ny*nz*nsub elements of the grid's
+ * storage type, 256-byte aligned), owned by the caller and released with
+ * bfvm_field_free; its contents are unspecified.  cand_ms (host
+ * [candidates], may be NULL) receives the timed sweep set of each
+ * candidate in ms, -1 for candidates not allocated.  With one candidate
+ * the call is a plain device allocation.  Synchronising.
+ * Errors: EINVAL (NULL grid or field, candidates outside [1, 16]), ESTATE
+ * (before set_params), ENOMEM, EDEVICE. */
+int bfvm_field_alloc(bfvm_grid g, int32_t candidates, void** field, float* cand_ms);
+/* Release a field allocated by bfvm_field_alloc (NULL is ignored).  The
+ * caller makes sure no enqueued work still uses it.  Errors: EDEVICE. */
+int bfvm_field_free(void* field);
+
 /* ---- batched domains -------------------------------------------------- */
 /*
  * Many independent grids (uneven sizes and substrate counts, any mix of
@@ -254,8 +281,14 @@ int bfvm_autotune(bfvm_grid g, void* field, int32_t reps, float* best_ms);
  * solver.  Not in the paper; the paper's closest knob is the block count of
  * its pipelined x sweep (Sec. 3.2, Eq. 5).
  *
- * The member grids are borrowed: they must stay alive, and their params,
- * sources and Dirichlet lists must not change, while the batch exists.
+ * The member grids are borrowed: they must stay alive while the batch
+ * exists.  Their params, sources and Dirichlet lists may change between
+ * batch calls (bfvm_set_params / set_sources / set_dirichlet on a member
+ * grid): every batch call that runs work first re-reads any grid changed
+ * since the batch last read it and rebuilds its programs, so the next
+ * bfvm_batch_step / step_adjoint captures its graph again.  A setter must
+ * not run while batch work is in flight (the batch calls below return only
+ * after their work has finished).
  * Line lengths up to 256 are supported, with line length x substrates at
  * most 2048 on every axis (e.g. 256 voxels x 8 substrates).  The batch's calls are not
  * thread-safe; calls on one batch from several threads must be serialised.
@@ -285,9 +318,10 @@ int bfvm_batch_set_mode(bfvm_batch b, int32_t mode);
  * run time. */
 int bfvm_batch_set_fields(bfvm_batch b, int32_t which, void* const* ptrs);
 
-/* nsteps steps of every domain by replaying the captured graph (captured on
- * the first call), then waits for the batch stream.  Errors: EINVAL,
- * EDEVICE. */
+/* nsteps steps of every domain by replaying the captured graph, then waits
+ * for the batch stream.  There is no separate capture call: the graph is
+ * captured on the first call (and again after a plan, mode or member-grid
+ * change).  Errors: EINVAL, EDEVICE. */
 int bfvm_batch_step(bfvm_batch b, int64_t nsteps);
 /* The same with the launches enqueued directly (no graph). */
 int bfvm_batch_step_eager(bfvm_batch b, int64_t nsteps);
