@@ -34,6 +34,7 @@ EXPORTS = [
     "bfvm_fill_uniform", "bfvm_fill_gaussian", "bfvm_device_bytes",
     "bfvm_timing_enable", "bfvm_timing_read", "bfvm_timing_reset", "bfvm_timing_elements",
     "bfvm_set_schedule", "bfvm_get_schedule", "bfvm_get_plan", "bfvm_set_plan", "bfvm_autotune",
+    "bfvm_field_alloc", "bfvm_field_free",
     "bfvm_batch_create", "bfvm_batch_destroy", "bfvm_batch_set_mode", "bfvm_batch_set_fields", "bfvm_batch_step",
     "bfvm_batch_step_eager", "bfvm_batch_step_adjoint", "bfvm_batch_autotune", "bfvm_batch_get_plan",
     "bfvm_batch_set_plan",
@@ -89,6 +90,8 @@ def lib():
     L.bfvm_get_plan.argtypes = [_vp, _i32, _i32p, _i32p, _i32p, _i32p]
     L.bfvm_set_plan.argtypes = [_vp, _i32, _i32, _i32, _i32, _i32]
     L.bfvm_autotune.argtypes = [_vp, _vp, _i32, ctypes.POINTER(ctypes.c_float)]
+    L.bfvm_field_alloc.argtypes = [_vp, _i32, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_float)]
+    L.bfvm_field_free.argtypes = [_vp]
     L.bfvm_batch_create.argtypes = [ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]
     L.bfvm_batch_destroy.argtypes = [_vp]
     L.bfvm_batch_set_fields.argtypes = [_vp, _i32, ctypes.POINTER(_vp)]
@@ -139,6 +142,25 @@ def _current_stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+class _FieldBuffer:
+    """Owner of a bfvm_field_alloc allocation, exposed to torch through the
+    CUDA array interface; torch keeps a reference for the tensor's lifetime,
+    and the memory is freed when the last reference goes."""
+
+    def __init__(self, ptr: int, shape, typestr: str):
+        self.ptr = ptr
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (ptr, False),
+                                         "strides": None, "version": 2}
+
+    def __del__(self):
+        try:
+            if self.ptr:
+                lib().bfvm_field_free(_vp(self.ptr))
+        except Exception:
+            pass
+        self.ptr = 0
+
+
 class Grid:
     """nx*ny*nz voxels x nsub substrates, spacings h (um), storage dtype."""
 
@@ -186,6 +208,22 @@ class Grid:
     def empty_field(self):
         import torch
         return torch.empty(self.shape, dtype=self.torch_dtype, device="cuda")
+
+    def alloc_field(self, candidates: int = 4):
+        """A field tensor in device memory whose placement the library chose
+        by timing the sweeps on `candidates` allocations (bfvm_field_alloc).
+        Returns (tensor, ms per candidate); the memory is released with the
+        last reference to the tensor.  Contents are unspecified."""
+        import torch
+        ptr = _vp()
+        ms = (ctypes.c_float * int(candidates))()
+        self._sync_stream()
+        _check(lib().bfvm_field_alloc(self._handle, int(candidates), ctypes.byref(ptr), ms), "bfvm_field_alloc")
+        buf = _FieldBuffer(ptr.value, self.shape, "<f8" if self.dtype == "f64" else "<f4")
+        t = torch.as_tensor(buf, device="cuda")
+        if t.data_ptr() != ptr.value or tuple(t.shape) != self.shape:
+            raise RuntimeError("field tensor does not wrap the allocation")
+        return t, [float(x) for x in ms]
 
     # -------------------------------------------------------------- setup
     def set_params(self, D, lam, dt: float):

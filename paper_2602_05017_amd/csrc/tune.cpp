@@ -119,3 +119,97 @@ int bfvm_autotune(bfvm_grid g, void* field, int32_t reps, float* best_ms)
     }
     return BFVM_OK;
 }
+
+// ------------------------------------------------------ field placement
+//
+// The sweep rate of one field depends on where its allocation lands in
+// device memory: on 1000^3 x 4 FP64 fields allocated side by side, the same
+// step took 38.4-38.6 ms on most allocations and 34.8-35.9 ms on one or two
+// of five, and each allocation kept its rate when measured again.  A
+// streaming in-place multiply ran at the same rate on all of them, so the
+// difference lies in how the sweeps' many concurrent row and plane streams
+// map onto the memory, not in the bytes moved.  The allocation is therefore
+// chosen by measurement: candidates are allocated side by side, each is
+// timed on one x, y and z sweep set, and the fastest is kept.
+
+namespace {
+
+// device memory to leave free while candidates are held
+size_t placement_reserve(size_t total) { return std::max<size_t>(total / 16, (size_t)4 << 30); }
+
+}  // namespace
+
+int bfvm_field_alloc(bfvm_grid g, int32_t candidates, void** field, float* cand_ms)
+{
+    if (!g) return tune_fail(BFVM_EINVAL, "grid is NULL");
+    if (!field) return tune_fail(BFVM_EINVAL, "field is NULL");
+    *field = nullptr;
+    if (candidates < 1 || candidates > 16) return tune_fail(BFVM_EINVAL, "candidates must be in [1, 16]");
+    if (!g->have_params) return tune_fail(BFVM_ESTATE, "set_params must come before field_alloc");
+    if (cand_ms)
+        for (int i = 0; i < candidates; ++i) cand_ms[i] = -1.0f;
+    const size_t bytes = (size_t)g->nelem() * bfvm::dtype_size(g->dtype);
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return tune_fail(BFVM_EDEVICE, "hipMemGetInfo");
+    const size_t reserve = placement_reserve(total_b);
+    int n = candidates;
+    while (n > 1 && (free_b < reserve || (size_t)n * bytes > free_b - reserve)) --n;
+    std::vector<void*> bufs;
+    for (int i = 0; i < n; ++i) {
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            break;
+        }
+        bufs.push_back(p);
+    }
+    if (bufs.empty()) return tune_fail(BFVM_ENOMEM, "device allocation of the field failed");
+    auto release_all_but = [&](size_t keep) {
+        (void)hipStreamSynchronize(g->stream);
+        for (size_t i = 0; i < bufs.size(); ++i)
+            if (i != keep) (void)hipFree(bufs[i]);
+    };
+    if (bufs.size() == 1) {
+        *field = bufs[0];
+        return BFVM_OK;
+    }
+    Events ev;
+    if (hipEventCreate(&ev.a) != hipSuccess || hipEventCreate(&ev.b) != hipSuccess) {
+        release_all_but(bufs.size());
+        return tune_fail(BFVM_EDEVICE, "hipEventCreate");
+    }
+    size_t best = 0;
+    float best_t = 0.0f;
+    for (size_t i = 0; i < bufs.size(); ++i) {
+        // bounded values (each sweep is a contraction), one warm-up set, one timed set
+        hipError_t e = bfvm::launch_fill_uniform(g->dtype, bufs[i], g->nelem(), 7, 0, 0.0, 1.0, g->stream);
+        int st = e == hipSuccess ? BFVM_OK : tune_fail(BFVM_EDEVICE, "fill kernel");
+        for (int a = 0; a < 3 && !st; ++a) st = bfvm_sweep(g, bufs[i], a);
+        if (!st && hipEventRecord(ev.a, g->stream) != hipSuccess) st = tune_fail(BFVM_EDEVICE, "hipEventRecord");
+        for (int a = 0; a < 3 && !st; ++a) st = bfvm_sweep(g, bufs[i], a);
+        float ms = 0.0f;
+        if (!st && (hipEventRecord(ev.b, g->stream) != hipSuccess || hipEventSynchronize(ev.b) != hipSuccess ||
+                    hipEventElapsedTime(&ms, ev.a, ev.b) != hipSuccess))
+            st = tune_fail(BFVM_EDEVICE, "event timing");
+        if (st) {
+            release_all_but(bufs.size());
+            return st;
+        }
+        if (cand_ms) cand_ms[i] = ms;
+        if (i == 0 || ms < best_t) {
+            best = i;
+            best_t = ms;
+        }
+    }
+    release_all_but(best);
+    *field = bufs[best];
+    return BFVM_OK;
+}
+
+int bfvm_field_free(void* field)
+{
+    if (!field) return BFVM_OK;
+    hipError_t e = hipFree(field);
+    if (e != hipSuccess) return tune_fail(BFVM_EDEVICE, std::string("hipFree: ") + hipGetErrorString(e));
+    return BFVM_OK;
+}
