@@ -1,11 +1,19 @@
 """Batched multi-domain form: uneven domains (each axis 24..192 voxels, 1..8
 substrates, FP32/FP64 storage mixed) stepped together, one graph replay per
-step.  Every domain is compared with the FP64 oracle at its storage type's
-bar and with its own single-grid GPU run within the same bar (the batch
-reads the Thomas constants from the global tables instead of LDS, which
-can change the rounding of individual products only through operation
-order, so equality is not required); graph replays must equal eager
-launches exactly.
+step.  Every batched result a test asserts is compared with the FP64 oracle
+at its storage type's bar: forward fields, and the reverse step's gradient
+field, dL/dD and dL/dlambda against the oracle's adjoint step on the same
+state and gradient.  Some tests compare with the domain's own single-grid
+GPU run as well (same bar; the batch reads the Thomas constants from its
+LDS copy of the tables, which changes only the operation order); graph
+replays must equal eager launches exactly.
+
+Adjoint bars against the oracle's FP64 adjoint of the state and gradient the
+GPU holds (FP32 values widened): the gradient field within 1e-12 (FP64
+storage) or 1e-5 (FP32 storage) normwise per substrate; dL/dD and
+dL/dlambda, sums of terms of both signs, within the normwise bars of
+gpu_helpers.param_grad_bars (the stored values' rounding carried through
+Cauchy-Schwarz, ||L_N||_2 <= 4 and 2-norm-contractive solves).
 
 Modes.  "grouped" (one launch per stage over all domains) is the library's
 default.  "persistent" (one launch per step, blocks waiting on per-stage
@@ -18,11 +26,27 @@ import pytest
 
 import oracle
 import workloads
-from gpu_helpers import make_grid, oracle_lists, rel_err, upload
+from gpu_helpers import (make_grid, one_substrate, oracle_adjoint, oracle_lists, param_grad_bars, rel_err, rel_vec,
+                         upload)
 
 pytestmark = pytest.mark.gpu
 
 TOL = {"f64": 1e-12, "f32": 1e-5, "f32fast": 1e-4}
+ADJ_TOL = {"f64": 1e-12, "f32": 1e-5, "f32fast": 1e-5}    # gradient field
+
+
+def _check_adjoint_vs_oracle(p, state, gin, got, gD, gL):
+    """Batched reverse step of domain p against the oracle's: the gradient
+    field normwise per substrate, dL/dD and dL/dlambda against their
+    normwise bars; returns (field e_max, |dD error| / bar, |dlambda error| / bar)."""
+    rg, rD, rL = oracle_adjoint(p, state, gin)
+    barD, barL = param_grad_bars(p, state, gin)
+    e = rel_err(got, rg)[0]
+    qD = float(np.max(np.abs(np.asarray(gD) - rD) / barD))
+    qL = float(np.max(np.abs(np.asarray(gL) - rL) / barL))
+    assert e <= ADJ_TOL[p.dtype] and qD <= 1.0 and qL <= 1.0, (p.name, p.dtype, e, qD, qL, rel_vec(gD, rD))
+    return e, qD, qL
+
 
 _PERSISTENT_OFF = ("persistent single-launch mode switched off: its cross-block dependency waits "
                    "did not complete on gfx950 (hung twice); not run until the cause is shown")
@@ -150,10 +174,15 @@ def test_batch_with_fp32_arithmetic_domains():
     off = 0
     for i in subset:
         p, g = probs[i], grids[i]
+        got = grads[i].double().cpu().numpy()
+        e = _check_adjoint_vs_oracle(p, g.read_field(fields[i]), gin[i].double().cpu().numpy(), got,
+                                     gD[off:off + p.S], gL[off:off + p.S])
+        print(f"{p.name} {p.dtype} batched reverse step vs oracle: grad {e[0]:.2e}, dD at {e[1]:.2f} "
+              f"and dlambda at {e[2]:.2f} of their bars")
         ref_g = gin[i].clone()
         rD, rL = g.step_adjoint(fields[i], ref_g)
         tol = TOL[p.dtype]
-        assert rel_err(grads[i].double().cpu().numpy(), ref_g.double().cpu().numpy())[0] <= tol, p.name
+        assert rel_err(got, ref_g.double().cpu().numpy())[0] <= tol, p.name
         assert np.max(np.abs(gL[off:off + p.S] - rL) / np.abs(rL)) <= max(tol, 1e-11), p.name
         off += p.S
     b.close()
@@ -190,7 +219,7 @@ def test_autotuner_picks_valid_plans_and_keeps_results(tmp_path, mode):
 
 
 @pytest.mark.parametrize("mode", MODES)
-def test_batch_adjoint_subset_matches_single_grid_adjoint(mode):
+def test_batch_adjoint_subset_matches_oracle_adjoint(mode):
     import torch
     import paper_2602_05017_amd as bf
     probs = _domains(9, lo=24, hi=64, nsteps=1, seed=1008)
@@ -221,11 +250,18 @@ def test_batch_adjoint_subset_matches_single_grid_adjoint(mode):
     off = 0
     for i in subset:
         p, g = probs[i], grids[i]
+        S = p.S
+        got = grads[i].double().cpu().numpy()
+        # the oracle's reverse step on the state and gradient the GPU holds
+        e = _check_adjoint_vs_oracle(p, g.read_field(fields[i]), gin[i].double().cpu().numpy(), got,
+                                     gD[off:off + S], gL[off:off + S])
+        print(f"{p.name} {p.dtype} {p.nx}x{p.ny}x{p.nz}x{S} batched reverse step vs oracle: grad {e[0]:.2e}, "
+              f"dD at {e[1]:.2f} and dlambda at {e[2]:.2f} of their bars")
+        # and the single-grid reverse step (the other kernel family) agrees
         ref_g = gin[i].clone()
         rD, rL = g.step_adjoint(fields[i], ref_g)
         tol = TOL[p.dtype]
-        assert rel_err(grads[i].double().cpu().numpy(), ref_g.double().cpu().numpy())[0] <= tol
-        S = p.S
+        assert rel_err(got, ref_g.double().cpu().numpy())[0] <= tol
         assert np.max(np.abs(gD[off:off + S] - rD) / np.abs(rD)) <= max(tol, 1e-11)
         assert np.max(np.abs(gL[off:off + S] - rL) / np.abs(rL)) <= max(tol, 1e-11)
         off += S
@@ -256,9 +292,14 @@ def test_persistent_mode_is_refused():
 
 
 def test_full_batch_workload_autotuned_100_steps():
-    # the benchmark's batch: 96 domains, autotuned plans, 100 graph replays;
-    # every domain against its own single-grid GPU run, and the two smallest
-    # domains of each storage type against the oracle
+    # the benchmark's batch: 96 domains, autotuned plans, 100 graph replays,
+    # then the reverse step of domains 0..31 on the final state, as the
+    # benchmark runs them.  Against the oracle (one substrate per domain:
+    # substrates do not couple): the largest domain of each storage type,
+    # the largest domain of each (storage type, axis) whose autotuned tile
+    # holds 16 elements per thread, and the two smallest of each storage
+    # type after 100 steps; every reverse step of the subset.  Every domain
+    # is also compared with its own single-grid GPU run.
     import torch
     import paper_2602_05017_amd as bf
     probs = workloads.batch_config()
@@ -266,12 +307,60 @@ def test_full_batch_workload_autotuned_100_steps():
     grids, fields = _setup(probs)
     b = bf.Batch(grids, fields)
     b.autotune(None)
+    plans = [[b.plan(d, a) for a in range(3)] for d in range(96)]
     for p, g, f in zip(probs, grids, fields):
         f.copy_(upload(p, g))
     torch.cuda.synchronize()
     b.step(100)
     got = [g.read_field(f) for g, f in zip(grids, fields)]
+    # reverse step of the 32-domain subset on the final state
+    subset = list(range(32))
+    rng = np.random.default_rng(1005)
+    gin = [(rng.random(probs[i].shape) - 0.5).astype(np.float64 if probs[i].dtype == "f64" else np.float32)
+           for i in subset]
+    grads = [torch.from_numpy(gin[i]).to("cuda") if i < 32 else None for i in range(96)]
+    b.set_grads(grads)
+    gD, gL = b.step_adjoint(subset)
+    gout = [grads[i].double().cpu().numpy() for i in subset]
     b.close()
+
+    size = {i: probs[i].V * probs[i].S for i in range(96)}
+    pick = {}
+    for dt in ("f64", "f32"):
+        of = sorted((i for i in range(96) if probs[i].dtype == dt), key=lambda i: size[i])
+        pick[of[-1]] = f"largest {dt}"
+        for i in of[:2]:
+            pick.setdefault(i, f"smallest {dt}")
+        for a in range(3):
+            m16 = [i for i in of if plans[i][a][0] == 16]
+            if m16:
+                pick.setdefault(m16[-1], f"largest {dt} with M=16 on axis {a}")
+    n16 = sum(plans[i][a][0] == 16 for i in range(96) for a in range(3))
+    print(f"autotuned: {n16} of 288 domain axes at M=16")
+    for i, why in sorted(pick.items()):
+        p = probs[i]
+        s = int(np.argmax(p.D))
+        q = one_substrate(p, s)
+        u = np.array(q.u0, copy=True)
+        src, dr = oracle_lists(q)
+        oracle.step(u, q.h, q.D, q.lam, q.dt, src, dr, 100)
+        e = rel_err(got[i][..., s:s + 1], u)[0]
+        print(f"{p.name} ({why}) {p.dtype} {p.nx}x{p.ny}x{p.nz}x{p.S} plans {plans[i]}, substrate {s}, "
+              f"100 steps vs oracle: e_max {e:.3e}")
+        assert e <= TOL[p.dtype], (p.name, e)
+    off = 0
+    worst = {}
+    for k, i in enumerate(subset):
+        p = probs[i]
+        s = k % p.S                     # sampled substrate
+        q = one_substrate(p, s)
+        st = got[i][..., s:s + 1]
+        e = _check_adjoint_vs_oracle(q, st, gin[k][..., s:s + 1], gout[k][..., s:s + 1],
+                                     gD[off + s:off + s + 1], gL[off + s:off + s + 1])
+        worst[p.dtype] = np.maximum(worst.get(p.dtype, np.zeros(3)), e)
+        off += p.S
+    print(f"32-domain batched reverse step vs oracle (one substrate each), worst (grad e_max, dD / bar, "
+          f"dlambda / bar): {worst}")
     worst = {}
     for p, out in zip(probs, got):
         single = make_grid(p, p.dtype)
@@ -284,16 +373,6 @@ def test_full_batch_workload_autotuned_100_steps():
         worst[p.dtype] = max(worst.get(p.dtype, 0.0), e)
         assert e <= TOL[p.dtype], (p.name, e)
     print(f"96 domains vs single-grid runs, 100 steps: worst e_max {worst}")
-    by_size = sorted(range(96), key=lambda k: probs[k].V * probs[k].S)
-    sample = [i for i in by_size if probs[i].dtype == "f64"][:2] + [i for i in by_size if probs[i].dtype == "f32"][:2]
-    for i in sample:
-        p = probs[i]
-        u = np.array(p.u0, copy=True)
-        src, dr = oracle_lists(p)
-        oracle.step(u, p.h, p.D, p.lam, p.dt, src, dr, 100)
-        e = rel_err(got[i], u)[0]
-        print(f"{p.name} {p.dtype} {p.nx}x{p.ny}x{p.nz}x{p.S} vs oracle, 100 steps: e_max {e:.3e}")
-        assert e <= TOL[p.dtype]
 
 
 def test_batch_rejects_tables_too_large_for_lds():
@@ -306,3 +385,53 @@ def test_batch_rejects_tables_too_large_for_lds():
         bf.Batch([g], [u])
     assert ei.value.code == "EINVAL"
     g.close()
+
+
+def test_batch_follows_member_grid_changes():
+    # params, sources and Dirichlet lists of member grids change after the
+    # batch was created (their device tables and lists are reallocated, with
+    # new lengths): the batch re-reads the grids and re-captures its graphs,
+    # so each domain follows the oracle run with the same change
+    import torch
+    import paper_2602_05017_amd as bf
+    probs = _domains(4, lo=24, hi=48, nsteps=2, seed=1014)
+    probs[2].dr = workloads.dirichlet_variant(probs[2], 6)
+    grids, fields = _setup(probs)
+    b = bf.Batch(grids, fields)
+    b.step(2)
+    ref = []
+    for p in probs:
+        u = np.array(p.u0, copy=True)
+        src, dr = oracle_lists(p)
+        oracle.step(u, p.h, p.D, p.lam, p.dt, src, dr, 2)
+        ref.append(u)
+    # domain 1: new D, lambda and dt; domain 2: a longer source list and no
+    # Dirichlet entries; domain 3: Dirichlet entries added
+    p1, p2, p3 = probs[1], probs[2], probs[3]
+    p1.D, p1.lam, p1.dt = p1.D * 2.5, p1.lam * 0.3, p1.dt * 1.5
+    grids[1].set_params(p1.D, p1.lam, p1.dt)
+    p2.src = workloads.make_sources(p2.seed + 7, p2.V, p2.S, 3 * len(p2.src))
+    grids[2].set_sources(p2.src.voxel, p2.src.secretion, p2.src.saturation, p2.src.uptake)
+    p2.dr = None
+    grids[2].set_dirichlet(np.zeros(0, dtype=np.int64), np.zeros(0), np.zeros(0, dtype=np.uint8))
+    p3.dr = workloads.dirichlet_variant(p3, 5)
+    grids[3].set_dirichlet(p3.dr.voxel, p3.dr.value, p3.dr.active)
+    b.step(2)
+    for k, (p, g, f) in enumerate(zip(probs, grids, fields)):
+        src, dr = oracle_lists(p)
+        oracle.step(ref[k], p.h, p.D, p.lam, p.dt, src, dr, 2)
+        e = rel_err(g.read_field(f), ref[k])[0]
+        assert e <= TOL[p.dtype], (k, p.dtype, e)
+    # the reverse step of the changed domains uses the new tables too
+    rng = np.random.default_rng(14)
+    gin = [(rng.random(p.shape) - 0.5).astype(np.float64 if p.dtype == "f64" else np.float32) for p in probs]
+    grads = [torch.from_numpy(x.copy()).to("cuda") for x in gin]
+    b.set_grads(grads)
+    gD, gL = b.step_adjoint([1, 2, 3])
+    off = 0
+    for i in (1, 2, 3):
+        p = probs[i]
+        _check_adjoint_vs_oracle(p, grids[i].read_field(fields[i]), gin[i], grads[i].double().cpu().numpy(),
+                                 gD[off:off + p.S], gL[off:off + p.S])
+        off += p.S
+    b.close()
