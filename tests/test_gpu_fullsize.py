@@ -3,10 +3,10 @@ configuration the benchmark times (default plans).
 
 - DCT-II eigenmode at full size: every sampled element must match the closed
   form u0 * prod_a mu_a^-m (a property that holds at any size).
-- One step with 1e6 source/sink voxels: the full substrate with the largest
-  D is compared element by element with the FP64 oracle (substrates do not
-  couple, so the oracle runs that substrate alone).
-- The same step with FP32 storage (FP64 arithmetic) against the oracle.
+- The benchmarked run (1e6 source/sink voxels, 20 steps): the substrates
+  with the smallest and the largest D are compared element by element with
+  the FP64 oracle (substrates do not couple, so the oracle runs each alone),
+  for FP64 storage and both FP32 forms.
 """
 import gc
 
@@ -121,32 +121,38 @@ def _one_substrate_reference(p, s, nsteps):
         src = oracle.Sources(p.src.voxel, p.src.secretion[:, s:s + 1], p.src.saturation[:, s:s + 1],
                              p.src.uptake[:, s:s + 1])
         oracle.step(u, p.h, p.D[s:s + 1], p.lam[s:s + 1], p.dt, src, None, nsteps)
-        _REF.clear()
+        if len(_REF) >= 2:
+            _REF.clear()
         _REF[key] = u[..., 0]
     return _REF[key]
 
 
-@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5), ("f32fast", 1e-5)])
 def test_tumour_scale_20_steps_vs_oracle(dtype, tol):
     # the benchmark's workload and launch configuration (default plans, 20
-    # steps); substrates do not couple, so the oracle runs the substrate with
-    # the largest D (largest r) alone
+    # steps), each storage form against the oracle; substrates do not couple,
+    # so the oracle runs the substrates with the smallest and the largest D
+    # (smallest and largest r: the two ends of the conditioning) alone, over
+    # every element of their fields.  FP32 arithmetic: r <= 2.8 here, where
+    # its measured error is 2.5e-6 after 20 steps, inside the FP32 bar
     import torch
     p = workloads.config(3)
     assert p.nsteps == 20
-    s = int(np.argmax(p.D))
+    subs = [int(np.argmin(p.D)), int(np.argmax(p.D))]
     g = make_grid(p, dtype)
     u = torch.from_numpy(p.u0).to(device="cuda", dtype=g.torch_dtype)
     g.step(u, p.nsteps)
     torch.cuda.synchronize()
-    got = u[..., s].cpu().numpy()
+    got = {s: u[..., s].cpu().numpy() for s in subs}
     g.close()
     del u
     _free()
-    ref = _one_substrate_reference(p, s, p.nsteps)
-    emax, e2 = rel_err(got[..., None], ref[..., None])
-    print(f"1000^3x4 {dtype}, substrate {s} (D={p.D[s]:.3g}), {p.nsteps} steps: e_max={emax:.3e} e_2={e2:.3e}")
-    assert emax <= tol
+    for s in subs:
+        ref = _one_substrate_reference(p, s, p.nsteps)
+        emax, e2 = rel_err(got[s][..., None], ref[..., None])
+        print(f"1000^3x4 {dtype}, substrate {s} (D={p.D[s]:.3g}), {p.nsteps} steps: e_max={emax:.3e} e_2={e2:.3e}")
+        assert emax <= tol
 
 
 def test_endtoend_pipeline_matches_oracle():

@@ -261,14 +261,29 @@ def test_fp32_storage_matches_the_oracle_rounded_per_stage():
     assert exact >= 0.99
 
 
-def test_fp32_fast_arithmetic_error_is_reported():
+def test_fp32_fast_arithmetic_within_the_fp32_bar():
     # FP32 arithmetic with coefficients rounded to FP32 drifts with r and the
-    # step count; the bound checked here is the one measured for r <= 10.
+    # step count.  The cells recipe at 40^3 x 4 has r <= 0.53; 20 steps stay
+    # within the FP32 form's 1e-5
     p = workloads.config(2, n=40, nsub=4, n_sources=2000, nsteps=20)
     ref = oracle_run(p)
     got = gpu_run(p, dtype="f32fast")
     emax, e2 = rel_err(got, ref)
-    print(f"f32fast 40^3x4, 20 steps: e_max={emax:.3e} e_2={e2:.3e}")
+    print(f"f32fast 40^3x4 (r <= 0.53), 20 steps: e_max={emax:.3e} e_2={e2:.3e}")
+    assert emax <= 1e-5
+
+
+def test_fp32_fast_arithmetic_at_r10_is_held_to_the_looser_bar():
+    # At r = 10 the rounded constants and FP32 recurrences accumulate to about
+    # 1.4e-5 after 20 steps (the coefficients' relative rounding 6e-8 grows
+    # with the conditioning, up to 1 + 2r = 21), above the FP32 bar: this
+    # case alone is held to 1e-4, and its error is reported
+    p = workloads.config(2, n=40, nsub=2, n_sources=2000, nsteps=20)
+    p.D = np.array([1.0e5, 1.0e5])        # r = dt D / h^2 = 10
+    ref = oracle_run(p)
+    got = gpu_run(p, dtype="f32fast")
+    emax, e2 = rel_err(got, ref)
+    print(f"f32fast 40^3x2 at r = 10, 20 steps: e_max={emax:.3e} e_2={e2:.3e}")
     assert emax <= 1e-4
 
 
