@@ -26,11 +26,21 @@ voxels, 1..8 substrates, FP32 or FP64 storage by a seeded coin, 1% of the
 voxels as sources), autotuned, stepped together by one graph replay per step
 (100 steps), plus the reverse step of domains 0..31.
 
+--workload ceiling: the device's streaming ceilings (write only, read only,
+in-place read+write, copy) on a 32 GB buffer.
+
+Fields are placed by the library (bfvm_field_alloc): the sweeps' rate depends
+on where a field's allocation lands in device memory, so --placement-candidates
+allocations (default 4) are timed on one sweep set each and the fastest is
+kept; the line reports every candidate and the step on a plain allocation.
+
 Prints ONE JSON line: voxel-substrate updates/s per LOD step, the roofline
 of the dominant kernel (algorithmic HBM bytes per launch / its mean launch
 time from HIP events on the grid's stream, against the 8 TB/s HBM peak),
-the same step with FP32 storage, and the FP64 oracle timed on the host on a
-bounded sample of the workload.
+the same step with FP32 storage (errors against the FP64 run per substrate,
+over every element), and the FP64 oracle timed on the host on a bounded
+sample of the workload, with the host's CPU and the oracle at one and at all
+threads on the three small workloads.
 """
 import argparse
 import hashlib
@@ -63,7 +73,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="liver",
                     choices=["liver", "cells", "gaussian", "batch", "adjoint", "liver4", "liver12", "liver16",
-                             "endtoend"])
+                             "endtoend", "ceiling"])
     ap.add_argument("--adjoint-steps", type=int, default=5,
                     help="batch workload: timed reverse steps of the 32-domain subset")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-storage companion run")
@@ -71,6 +81,8 @@ def parse():
     ap.add_argument("--cpu-sample-steps", type=int, default=10)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 4 GiB buffer twice (reference for FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--placement-candidates", type=int, default=4,
+                    help="allocations the library times to place each field (1: a plain allocation)")
     return ap.parse_args()
 
 
@@ -109,11 +121,22 @@ def make_grid(p, dtype):
     return g
 
 
-def timed_run(p, dtype, steps, warmup, u_host):
-    """Warm up, reload the field, then time `steps` steps; per-stage HIP-event times."""
+def timed_run(p, dtype, steps, warmup, u_host, candidates=1):
+    """Warm up, reload the field, then time `steps` steps; per-stage HIP-event times.
+    The field is placed by the library (bfvm_field_alloc) among `candidates`
+    allocations; with 1 it is a plain torch allocation."""
     import torch
     g = make_grid(p, dtype)
-    u = torch.empty(p.shape, dtype=g.torch_dtype, device="cuda")
+    placement = None
+    if candidates > 1:
+        u, cand_ms = g.alloc_field(candidates)
+        ok = [m for m in cand_ms if m >= 0]
+        placement = {"candidates": len(ok), "candidate_sweep_set_ms": [round(m, 3) for m in ok],
+                     "kept": int(np.argmin(ok))}
+        log(f"{dtype}: placement among {len(ok)} allocations, x+y+z sweep set "
+            f"{', '.join(f'{m:.2f}' for m in ok)} ms; kept #{placement['kept']}")
+    else:
+        u = torch.empty(p.shape, dtype=g.torch_dtype, device="cuda")
     u.copy_(u_host)
     g.step(u, warmup)
     torch.cuda.synchronize()
@@ -134,7 +157,52 @@ def timed_run(p, dtype, steps, warmup, u_host):
         stages[name] = {"total_ms": ms, "launches": n, "avg_ms": ms / n if n else 0.0,
                         "elements_per_launch": elems / n if n else 0}
     g.timing(False)
-    return g, u, t, stages
+    return g, u, t, stages, placement
+
+
+def default_allocation_ms(p, dtype, steps=5):
+    """ms per step on a plain torch allocation of the field (for comparison
+    with the placed one); the field is written on the device."""
+    import torch
+    g = make_grid(p, dtype)
+    u = torch.empty(p.shape, dtype=g.torch_dtype, device="cuda")
+    g.fill_uniform(u, p.seed, 0)
+    g.step(u, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(u, steps)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    g.close()
+    del u
+    torch.cuda.empty_cache()
+    return round(1e3 * t, 3)
+
+
+def fp32_error(u32, u64, slab=50):
+    """Per-substrate errors of an FP32-storage field against the FP64 GPU
+    field over every element, streamed in z-slabs on the device:
+    e_max = max|d| / max|u64| and e_2 = ||d||_2 / ||u64||_2."""
+    import torch
+    S = u64.shape[-1]
+    dmax = torch.zeros(S, dtype=torch.float64, device=u64.device)
+    rmax = torch.zeros_like(dmax)
+    d2 = torch.zeros_like(dmax)
+    r2 = torch.zeros_like(dmax)
+    for z0 in range(0, u64.shape[0], slab):
+        a = u64[z0:z0 + slab].reshape(-1, S)
+        d = u32[z0:z0 + slab].reshape(-1, S).double() - a
+        dmax = torch.maximum(dmax, d.abs().amax(0))
+        rmax = torch.maximum(rmax, a.abs().amax(0))
+        d2 += (d * d).sum(0)
+        r2 += (a * a).sum(0)
+        del d
+    emax = (dmax / rmax).cpu().numpy()
+    e2 = (d2.sqrt() / r2.sqrt()).cpu().numpy()
+    return {"e_max_per_substrate": [float(f"{x:.4g}") for x in emax],
+            "e_2_per_substrate": [float(f"{x:.4g}") for x in e2],
+            "e_max": float(f"{emax.max():.4g}"), "e_2": float(f"{e2.max():.4g}"),
+            "reference": "FP64 GPU run of the same workload, every element"}
 
 
 SWEEP_SOURCES = ["sweep.hip", "seg_solver.hpp", "internal.hpp"]
@@ -161,6 +229,60 @@ def traffic_record(workload_name, dtype, kernel_stage):
     if not k:
         return None
     return k.get("hbm_bytes_per_launch")
+
+
+def host_info():
+    """CPU model, hardware threads and memory of the host the oracle runs on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    ram = None
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                ram = round(int(line.split()[1]) / (1 << 20), 1)
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "threads_available": len(os.sched_getaffinity(0)),
+            "ram_GiB": ram}
+
+
+def oracle_thread_runs():
+    """The oracle on the three small workloads at one thread and at every
+    host thread it is allowed (bounded samples: the whole 64^3 x 1 run, one
+    step of the 256^3 x 8 workload with its sources and Dirichlet voxels,
+    five steps of the 128^3 x 2 workload)."""
+    import oracle
+    import workloads
+    full = oracle.threads()
+    cases = [("gaussian-64^3x1-f64 (10 steps)", workloads.config(1), 10),
+             ("cells-256^3x8-f64 (1 of 100 steps)", workloads.config(2), 1),
+             ("adjoint-128^3x2 forward (5 of 50 steps)", workloads.config(4), 5)]
+    out = {}
+    for name, p, n in cases:
+        src = dr = None
+        if p.src is not None:
+            src = oracle.Sources(p.src.voxel, p.src.secretion, p.src.saturation, p.src.uptake)
+        if p.dr is not None:
+            dr = oracle.Dirichlet(p.dr.voxel, p.dr.value, p.dr.active)
+        rec = {}
+        for th in (1, full):
+            oracle.set_threads(th)
+            u = np.array(p.u0, copy=True)
+            t0 = time.perf_counter()
+            oracle.step(u, p.h, p.D, p.lam, p.dt, src, dr, n)
+            t = time.perf_counter() - t0
+            rec[f"{th}_thread{'s' if th > 1 else ''}"] = {"updates_per_s": p.V * p.S * n / t,
+                                                          "ms_per_step": round(1e3 * t / n, 2)}
+        out[name] = rec
+    oracle.set_threads(full)
+    return out
 
 
 def cpu_baseline(p, sample_steps):
@@ -368,6 +490,11 @@ def run_adjoint(args):
 # The paper's own step times for these cubes (Table 1, BioFVM-B, FP64 with
 # AVX256D on MareNostrum 5 nodes of 2 x Xeon Platinum 8480+): context for the
 # line, not a target of this measurement.
+PAPER_TABLE2_8PCT = {"case": "8% liver, 1000^3 x 4 (the paper's second table)", "BioFVM-B_ms_per_step": 270,
+                     "BioFVM-X_ms_per_step": 2390, "nodes": 8,
+                     "hardware": "MareNostrum 5 nodes of 2 x Xeon Platinum 8480+ (112 cores), FP64 with AVX256D, "
+                                 "one MPI rank and 112 OpenMP threads per node"}
+
 PAPER_TABLE1 = {
     "liver4": {"BioFVM-B_ms_per_step": 107.5, "nodes": 1, "BioFVM_ms": 241.4, "BioFVM-X_ms": 469},
     "liver12": {"BioFVM-B_ms_per_step": 356.1, "nodes": 48},
@@ -386,7 +513,11 @@ def run_large(args):
     e = 8 if p.dtype == "f64" else 4
     log(f"workload {p.name}: {upd:.4g} voxel-substrates, field {upd * e / 1e9:.0f} GB, sources {len(p.src)}")
     g = make_grid(p, p.dtype)
-    u = torch.empty(p.shape, dtype=g.torch_dtype, device="cuda")
+    # the library places the field among as many candidate allocations as
+    # fit beside it (one for the 216 GB and 256 GB cubes)
+    u, cand_ms = g.alloc_field(args.placement_candidates)
+    ok = [m for m in cand_ms if m >= 0]
+    placement = {"candidates": max(1, len(ok)), "candidate_sweep_set_ms": [round(m, 3) for m in ok]}
     t0 = time.perf_counter()
     g.fill_uniform(u, p.seed, 0)
     torch.cuda.synchronize()
@@ -432,6 +563,7 @@ def run_large(args):
                      "stages_ms_per_step": {k: round(v["total_ms"] / steps, 3) for k, v in stages.items()}},
         "memory": {"field_bytes": upd * e, "library_bytes": lib_bytes,
                    "bytes_per_voxel_substrate": round((upd * e + lib_bytes) / upd, 3)},
+        "placement": placement,
         "cpu_baseline": None,
     }
     if args.workload in PAPER_TABLE1:
@@ -544,6 +676,52 @@ def rmw_ceiling(u, reps: int = 3):
             "bytes": nbytes}
 
 
+def run_ceiling(args):
+    """Streaming ceilings of the device on a buffer the size of the
+    1000^3 x 4 FP64 field (32 GB), with torch's vectorised kernels: write
+    only (fill), read only (sum), in-place read+write (multiply by 1.0) and
+    copy between two halves.  Each is timed with events over `steps` passes
+    after one untimed pass.  A sweep reads and writes every element once,
+    so the in-place read+write rate bounds what a sweep can reach."""
+    import torch
+    reps = 5 if args.steps is None else args.steps
+    n = 1000 ** 3 * 4
+    u = torch.empty(n, dtype=torch.float64, device="cuda")
+    u.fill_(0.5)
+    half = n // 2
+    out = {}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    nb = n * 8
+    for name, fn, moved in (("write_only", lambda: u.fill_(0.5), nb), ("read_only", lambda: u.sum(), nb),
+                            ("in_place_read_write", lambda: u.mul_(1.0), 2 * nb),
+                            ("copy", lambda: u[half:].copy_(u[:half]), nb)):
+        ms = timed(fn)
+        gbps = moved / (ms * 1e-3) / 1e9
+        out[name] = {"GBps": round(gbps, 1), "frac_of_peak": round(gbps / HBM_PEAK_GBPS, 4), "ms": round(ms, 3),
+                     "bytes": moved}
+        log(f"{name}: {gbps:.0f} GB/s ({gbps / HBM_PEAK_GBPS:.1%} of peak)")
+    best = out["in_place_read_write"]["GBps"]
+    line = {"metric": "HBM streaming ceiling (read+write in place)", "value": best, "unit": "GB/s", "n_gpus": 1,
+            "steps": reps, "warmup": 1, "ms_per_step": out["in_place_read_write"]["ms"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic (constant buffer)",
+            "config": {"workload": "streaming ceilings on a 32 GB buffer (the 1000^3 x 4 FP64 field size)"},
+            "roofline": {"bound": "hbm", "achieved": best, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": round(best / HBM_PEAK_GBPS, 4), "traffic": None},
+            "patterns": out, "cpu_baseline": None}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -567,6 +745,9 @@ def main():
     if args.workload == "endtoend":
         run_endtoend(args)
         return
+    if args.workload == "ceiling":
+        run_ceiling(args)
+        return
     if args.steps is None:
         args.steps = 20
     p = workload(args.workload)
@@ -575,7 +756,7 @@ def main():
     u_host = torch.from_numpy(p.u0)
     upd_per_step = p.V * p.S
 
-    g, u, t, stages = timed_run(p, "f64", args.steps, args.warmup, u_host)
+    g, u, t, stages, placement = timed_run(p, "f64", args.steps, args.warmup, u_host, args.placement_candidates)
     ms_per_step = 1e3 * t / args.steps
     value = upd_per_step * args.steps / t
     log(f"f64: {ms_per_step:.3f} ms/step, {value:.4g} updates/s")
@@ -592,9 +773,9 @@ def main():
                 "avg_launch_ms": round(sweeps[dom]["avg_ms"], 5),
                 "launches_per_step": sweeps[dom]["launches"] // args.steps,
                 "step_alg_GBps": round(3 * 2 * 8 * upd_per_step / (ms_per_step * 1e-3) / 1e9, 1),
+                "step_frac": round(3 * 2 * 8 * upd_per_step / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
                 "schedule": {"fused_yz_slabs": sched[0] == 1, "slab_width": sched[1]},
                 "stages_ms_per_step": {k: round(v["total_ms"] / args.steps, 4) for k, v in stages.items()}}
-    fp64_ref = u[..., 0].flatten()[:: 997].double().cpu() if not args.no_fp32 else None
     roofline["practical_ceiling"] = rmw_ceiling(u)
     roofline["frac_of_practical_ceiling"] = round(roofline["step_alg_GBps"] / roofline["practical_ceiling"]["GBps"], 4)
     log(f"in-place read+write ceiling on the same field: {roofline['practical_ceiling']['GBps']:.0f} GB/s; "
@@ -603,49 +784,49 @@ def main():
     memory = {"field_bytes": upd_per_step * 8, "library_bytes": lib_bytes,
               "bytes_per_voxel_substrate": round((upd_per_step * 8 + lib_bytes) / upd_per_step, 3)}
     g.close()
-    del u
-    torch.cuda.empty_cache()
+    if placement is not None:
+        placement["default_allocation_ms_per_step"] = default_allocation_ms(p, "f64")
+        log(f"the same step on a plain allocation: {placement['default_allocation_ms_per_step']} ms")
 
     fp32 = None
     if not args.no_fp32:
-        g32, u32, t32, st32 = timed_run(p, "f32", args.steps, args.warmup, u_host)
-        v32 = upd_per_step * args.steps / t32
-        s32 = {k: v for k, v in st32.items() if k.startswith("sweep")}
-        d32 = max(s32, key=lambda k: s32[k]["total_ms"])
-        ach32 = 2 * 4 * s32[d32]["elements_per_launch"] / (s32[d32]["avg_ms"] * 1e-3) / 1e9
-        samp = u32[..., 0].flatten()[:: 997].double().cpu()
-        err = float((samp - fp64_ref).abs().max() / fp64_ref.abs().max())
-        fp32 = {"value": v32, "ms_per_step": round(1e3 * t32 / args.steps, 3),
-                "dtype": "f32 storage, f64 arithmetic",
-                "dominant_kernel_GBps": round(ach32, 1), "frac": round(ach32 / HBM_PEAK_GBPS, 4),
-                "max_rel_diff_vs_f64_sampled": err}
-        log(f"f32: {fp32['ms_per_step']} ms/step, {v32:.4g} updates/s, sampled diff vs f64 {err:.2e}")
-        g32.close()
-        del u32
-        torch.cuda.empty_cache()
-        # FP32 storage and FP32 sweeps (constants precomputed in FP64, rounded)
-        gf, uf, tf, stf = timed_run(p, "f32fast", args.steps, args.warmup, u_host)
-        vf = upd_per_step * args.steps / tf
-        sf = {k: v for k, v in stf.items() if k.startswith("sweep")}
-        df = max(sf, key=lambda k: sf[k]["total_ms"])
-        achf = 2 * 4 * sf[df]["elements_per_launch"] / (sf[df]["avg_ms"] * 1e-3) / 1e9
-        sampf = uf[..., 0].flatten()[:: 997].double().cpu()
-        errf = float((sampf - fp64_ref).abs().max() / fp64_ref.abs().max())
-        fp32["fp32_arithmetic"] = {"value": vf, "ms_per_step": round(1e3 * tf / args.steps, 3),
-                                   "dtype": "f32 storage, f32 arithmetic, f64-precomputed constants",
-                                   "dominant_kernel_GBps": round(achf, 1), "frac": round(achf / HBM_PEAK_GBPS, 4),
-                                   "max_rel_diff_vs_f64_sampled": errf}
-        log(f"f32 arithmetic: {fp32['fp32_arithmetic']['ms_per_step']} ms/step, {vf:.4g} updates/s, "
-            f"sampled diff vs f64 {errf:.2e}")
-        gf.close()
-        del uf
-        torch.cuda.empty_cache()
+        # the FP64 field stays resident: the FP32 runs are compared with it element by element
+        for dtype in ("f32", "f32fast"):
+            g32, u32, t32, st32, pl32 = timed_run(p, dtype, args.steps, args.warmup, u_host,
+                                                  args.placement_candidates)
+            v32 = upd_per_step * args.steps / t32
+            s32 = {k: v for k, v in st32.items() if k.startswith("sweep")}
+            d32 = max(s32, key=lambda k: s32[k]["total_ms"])
+            ach32 = 2 * 4 * s32[d32]["elements_per_launch"] / (s32[d32]["avg_ms"] * 1e-3) / 1e9
+            err = fp32_error(u32, u)
+            rec = {"value": v32, "ms_per_step": round(1e3 * t32 / args.steps, 3),
+                   "dtype": "f32 storage, f64 arithmetic" if dtype == "f32" else
+                            "f32 storage, f32 arithmetic, f64-precomputed constants",
+                   "dominant_kernel": KERNEL_NAMES[d32], "dominant_kernel_GBps": round(ach32, 1),
+                   "frac": round(ach32 / HBM_PEAK_GBPS, 4),
+                   "step_alg_GBps": round(3 * 2 * 4 * upd_per_step / (t32 / args.steps) / 1e9, 1),
+                   "error_vs_f64": err, "placement": pl32,
+                   "stages_ms_per_step": {k: round(v["total_ms"] / args.steps, 4) for k, v in st32.items()}}
+            log(f"{dtype}: {rec['ms_per_step']} ms/step, {v32:.4g} updates/s, vs f64 e_max {err['e_max']:.2e} "
+                f"e_2 {err['e_2']:.2e} (per substrate {err['e_max_per_substrate']})")
+            g32.close()
+            del u32
+            torch.cuda.empty_cache()
+            if dtype == "f32":
+                fp32 = rec
+            else:
+                fp32["fp32_arithmetic"] = rec
+    del u
+    torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         cpu = cpu_baseline(p, args.cpu_sample_steps)
         log(f"oracle: {cpu['value']:.4g} updates/s on {cpu['cores']} threads")
+        cpu["host"] = host_info()
+        cpu["small_workloads"] = oracle_thread_runs()
+        log(f"host {cpu['host']}; oracle on the small workloads: {json.dumps(cpu['small_workloads'])}")
 
     line = {
         "metric": "voxel-substrate updates/s per LOD step (FP64)",
@@ -665,10 +846,13 @@ def main():
                    "dirichlet": 0 if p.dr is None else len(p.dr), "dt_min": p.dt,
                    "h_um": list(map(float, p.h))},
         "roofline": roofline,
+        "placement": placement,
         "fp32": fp32,
         "memory": memory,
         "cpu_baseline": cpu,
     }
+    if args.workload == "liver":
+        line["paper_context"] = PAPER_TABLE2_8PCT
     print(json.dumps(line), flush=True)
 
 

@@ -69,6 +69,8 @@ def _load():
                                         _i64, _i64p, _f64p, _u8p]
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = None
     for name in ("oracle_sweep", "oracle_source", "oracle_dirichlet", "oracle_step",
                  "oracle_adjoint_step"):
         getattr(lib, name).restype = ctypes.c_int
@@ -79,6 +81,11 @@ def _load():
 def threads() -> int:
     """OpenMP threads the oracle's sweeps run on."""
     return int(_load().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Run the following oracle calls on n OpenMP threads."""
+    _load().oracle_set_threads(int(n))
 
 
 def _p(a, t=_f64p):

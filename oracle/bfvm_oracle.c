@@ -52,6 +52,13 @@
 /* Number of OpenMP threads the sweeps use (reported with CPU timings). */
 int oracle_threads(void) { return omp_get_max_threads(); }
 
+/* Thread count for the following calls (baseline timing at one thread and at
+ * all host threads); n < 1 leaves it unchanged. */
+void oracle_set_threads(int n)
+{
+    if (n >= 1) omp_set_num_threads(n);
+}
+
 /* ---------------------------------------------------------------- O1-O3 */
 
 /* Thomas factors of the (n x n) matrix of O2 with parameters r, beta.
