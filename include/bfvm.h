@@ -136,6 +136,24 @@ int bfvm_sweep(bfvm_grid g, void* field, int32_t axis);
 int bfvm_step_adjoint(bfvm_grid g, const void* field_in, void* grad,
                       double* grad_D, double* grad_lambda);
 
+/* bfvm_step_adjoint for callers that cannot allocate device memory: code
+ * under graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results and synchronisation as
+ * bfvm_step_adjoint, and the same kernels; the workspace (three sweep
+ * outputs, reduction partials and results) comes from a device array of
+ * 97 MiB that the library's code object carries (each GPU the library
+ * runs on holds one copy until the process ends) instead of allocations.
+ * The call allocates no device memory, and no host memory except to
+ * format an error message.  Limit: 3 * (field bytes,
+ * rounded up to 256) + the reduction partials (48 KiB per substrate) +
+ * 48 B per substrate must fit in 97 MiB; the 128^3 x 2 FP64 grid does
+ * (e.g. 96 MiB of sweep outputs).  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (several threads or streams) race.
+ * Errors: EINVAL (NULL pointers, grid too large: nothing is enqueued),
+ * ESTATE, EDEVICE. */
+int bfvm_step_adjoint_noalloc(bfvm_grid g, const void* field_in, void* grad, double* grad_D,
+                              double* grad_lambda);
+
 /* Device memory the library holds for this grid (coefficient tables, source
  * and Dirichlet lists, adjoint workspace once allocated), in bytes, as the
  * HIP runtime sizes the allocations; the caller-owned fields are not

@@ -29,7 +29,8 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ERANGE", -3: "ESTATE", -4: "EDEVICE", -5: 
 # every entry point declared in include/bfvm.h
 EXPORTS = [
     "bfvm_create", "bfvm_destroy", "bfvm_set_stream", "bfvm_set_params", "bfvm_set_sources",
-    "bfvm_set_dirichlet", "bfvm_step", "bfvm_sweep", "bfvm_step_adjoint", "bfvm_read_field",
+    "bfvm_set_dirichlet", "bfvm_step", "bfvm_sweep", "bfvm_step_adjoint", "bfvm_step_adjoint_noalloc",
+    "bfvm_read_field",
     "bfvm_save_npy", "bfvm_load_npy",
     "bfvm_fill_uniform", "bfvm_fill_gaussian", "bfvm_device_bytes",
     "bfvm_timing_enable", "bfvm_timing_read", "bfvm_timing_reset", "bfvm_timing_elements",
@@ -78,6 +79,7 @@ def lib():
     L.bfvm_step.argtypes = [_vp, _vp, _i64]
     L.bfvm_sweep.argtypes = [_vp, _vp, _i32]
     L.bfvm_step_adjoint.argtypes = [_vp, _vp, _vp, _f64p, _f64p]
+    L.bfvm_step_adjoint_noalloc.argtypes = [_vp, _vp, _vp, _f64p, _f64p]
     L.bfvm_read_field.argtypes = [_vp, _vp, _vp]
     L.bfvm_save_npy.argtypes = [_vp, _vp, ctypes.c_char_p]
     L.bfvm_load_npy.argtypes = [_vp, _vp, ctypes.c_char_p]

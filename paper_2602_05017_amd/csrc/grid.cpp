@@ -370,6 +370,83 @@ int check_grid(bfvm_grid g)
 
 }  // namespace
 
+namespace bfvm {
+
+int64_t adjoint_partials_count(bfvm_grid g) { return 3 * 2 * (int64_t)g->S * adjoint_reduce_blocks(g->nvox()); }
+
+// One reverse step into caller-provided workspace: work[3] field buffers,
+// partials (adjoint_partials_count doubles), red_out (6 S doubles).
+// Enqueues on the grid's stream, then reads the reductions back in chunks
+// of substrates through a stack buffer and increments grad_D, grad_lambda.
+// Allocates nothing.
+int adjoint_step_into(bfvm_grid g, const void* field_in, void* grad, void* const work[3], double* partials,
+                      double* red_out, double* grad_D, double* grad_lambda)
+{
+    const size_t bytes = (size_t)g->nelem() * dtype_size(g->dtype);
+    const int S = g->S;
+    const int64_t nb = adjoint_reduce_blocks(g->nvox());
+    hipStream_t st = g->stream;
+    int rc;
+    // forward recomputation: work[a] = output of sweep a (before the following
+    // Dirichlet overwrite).  Without Dirichlet entries sweep a reads work[a-1]
+    // directly; with them it runs on an overwritten copy, so that work[a-1]
+    // keeps the sweep output the reduction needs.  Without sources either,
+    // nothing changes the state before the x sweep, which then reads field_in
+    // itself instead of a copy.
+    if (g->nsrc == 0 && g->ndir == 0) {
+        if ((rc = run_sweep(g, 0, field_in, work[0], false))) return rc;
+    } else {
+        HIP_TRY(hipMemcpyAsync(work[0], field_in, bytes, hipMemcpyDeviceToDevice, st), "copy");
+        if ((rc = run_source(g, work[0]))) return rc;
+        if ((rc = run_dirichlet(g, work[0]))) return rc;
+        if ((rc = run_sweep(g, 0, work[0], work[0], false))) return rc;
+    }
+    for (int a = 1; a < 3; ++a) {
+        if (g->ndir > 0) {
+            HIP_TRY(hipMemcpyAsync(work[a], work[a - 1], bytes, hipMemcpyDeviceToDevice, st), "copy");
+            if ((rc = run_dirichlet(g, work[a]))) return rc;
+            if ((rc = run_sweep(g, a, work[a], work[a], false))) return rc;
+        } else if ((rc = run_sweep(g, a, work[a - 1], work[a], false))) {
+            return rc;
+        }
+    }
+    // reverse: Dir^T, Z^T, Dir^T, Y^T, Dir^T, X^T, Dir^T, Src^T
+    for (int a = 2; a >= 0; --a) {
+        hipError_t e = launch_mask(g->dtype, grad, g->dir_elem, g->ndir, st);
+        if (e != hipSuccess) return hip_fail(e, "mask kernel");
+        if ((rc = run_sweep(g, a, grad, grad, true))) return rc;
+        const AxisGeom geo = axis_geom(a, g->nx, g->ny, g->nz, S);
+        e = launch_adjoint_partials(g->dtype, grad, work[a], geo, g->nelem(), partials + a * 2 * S * nb, nb, st);
+        if (e != hipSuccess) return hip_fail(e, "adjoint reduction");
+    }
+    hipError_t ef = launch_adjoint_final(partials, nb, S, 3, red_out, st);
+    if (ef != hipSuccess) return hip_fail(ef, "adjoint reduction");
+    hipError_t e = launch_mask(g->dtype, grad, g->dir_elem, g->ndir, st);
+    if (e != hipSuccess) return hip_fail(e, "mask kernel");
+    e = launch_source_transpose(g->dtype, grad, g->src_vox, g->src_invQ, g->nsrc, S, st);
+    if (e != hipSuccess) return hip_fail(e, "source transpose kernel");
+    // red_out[(a*S + s)*2 + {0, 1}]: sums of y^T (L_N x) and y^T x.
+    // dL/dr_a = -sum y^T L_N x, dL/dbeta = -sum y^T x; dr_a/dD = dt/h_a^2, dbeta/dlambda = dt/3
+    constexpr int kChunk = 64;
+    double buf[3][2 * kChunk];
+    for (int s0 = 0; s0 < S; s0 += kChunk) {
+        const int cnt = std::min(kChunk, S - s0);
+        for (int a = 0; a < 3; ++a)
+            HIP_TRY(hipMemcpyAsync(buf[a], red_out + 2 * ((int64_t)a * S + s0), sizeof(double) * 2 * cnt,
+                                   hipMemcpyDeviceToHost, st),
+                    "copy reductions");
+        HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+        for (int k = 0; k < cnt; ++k)
+            for (int a = 0; a < 3; ++a) {
+                grad_D[s0 + k] += -buf[a][2 * k + 0] * g->dt / (g->h[a] * g->h[a]);
+                grad_lambda[s0 + k] += -buf[a][2 * k + 1] * g->dt / 3.0;
+            }
+    }
+    return BFVM_OK;
+}
+
+}  // namespace bfvm
+
 // ======================================================================= ABI
 
 extern "C" {
@@ -660,59 +737,7 @@ int bfvm_step_adjoint(bfvm_grid g, const void* field_in, void* grad, double* gra
         g->red_blocks = nb;
     }
     if (!g->red_out) HIP_TRY(hipMalloc((void**)&g->red_out, sizeof(double) * 2 * S * 3), "hipMalloc red_out");
-    hipStream_t st = g->stream;
-    int rc;
-    // forward recomputation: work[a] = output of sweep a (before the following
-    // Dirichlet overwrite).  Without Dirichlet entries sweep a reads work[a-1]
-    // directly; with them it runs on an overwritten copy, so that work[a-1]
-    // keeps the sweep output the reduction needs.  Without sources either,
-    // nothing changes the state before the x sweep, which then reads field_in
-    // itself instead of a copy.
-    if (g->nsrc == 0 && g->ndir == 0) {
-        if ((rc = run_sweep(g, 0, field_in, g->work[0], false))) return rc;
-    } else {
-        HIP_TRY(hipMemcpyAsync(g->work[0], field_in, bytes, hipMemcpyDeviceToDevice, st), "copy");
-        if ((rc = run_source(g, g->work[0]))) return rc;
-        if ((rc = run_dirichlet(g, g->work[0]))) return rc;
-        if ((rc = run_sweep(g, 0, g->work[0], g->work[0], false))) return rc;
-    }
-    for (int a = 1; a < 3; ++a) {
-        if (g->ndir > 0) {
-            HIP_TRY(hipMemcpyAsync(g->work[a], g->work[a - 1], bytes, hipMemcpyDeviceToDevice, st), "copy");
-            if ((rc = run_dirichlet(g, g->work[a]))) return rc;
-            if ((rc = run_sweep(g, a, g->work[a], g->work[a], false))) return rc;
-        } else if ((rc = run_sweep(g, a, g->work[a - 1], g->work[a], false))) {
-            return rc;
-        }
-    }
-    // reverse: Dir^T, Z^T, Dir^T, Y^T, Dir^T, X^T, Dir^T, Src^T
-    for (int a = 2; a >= 0; --a) {
-        hipError_t e = launch_mask(g->dtype, grad, g->dir_elem, g->ndir, st);
-        if (e != hipSuccess) return hip_fail(e, "mask kernel");
-        if ((rc = run_sweep(g, a, grad, grad, true))) return rc;
-        const AxisGeom geo = axis_geom(a, g->nx, g->ny, g->nz, S);
-        e = launch_adjoint_partials(g->dtype, grad, g->work[a], geo, g->nelem(), g->red_partials + a * 2 * S * nb,
-                                    nb, st);
-        if (e != hipSuccess) return hip_fail(e, "adjoint reduction");
-    }
-    hipError_t ef = launch_adjoint_final(g->red_partials, nb, S, 3, g->red_out, st);
-    if (ef != hipSuccess) return hip_fail(ef, "adjoint reduction");
-    hipError_t e = launch_mask(g->dtype, grad, g->dir_elem, g->ndir, st);
-    if (e != hipSuccess) return hip_fail(e, "mask kernel");
-    e = launch_source_transpose(g->dtype, grad, g->src_vox, g->src_invQ, g->nsrc, S, st);
-    if (e != hipSuccess) return hip_fail(e, "source transpose kernel");
-    std::vector<double> red(2 * S * 3);
-    HIP_TRY(hipMemcpyAsync(red.data(), g->red_out, sizeof(double) * red.size(), hipMemcpyDeviceToHost, st),
-            "copy reductions");
-    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
-    // dL/dr_a = -sum y^T L_N x, dL/dbeta = -sum y^T x; dr_a/dD = dt/h_a^2, dbeta/dlambda = dt/3
-    for (int s = 0; s < S; ++s) {
-        for (int a = 0; a < 3; ++a) {
-            grad_D[s] += -red[2 * S * a + 2 * s + 0] * g->dt / (g->h[a] * g->h[a]);
-            grad_lambda[s] += -red[2 * S * a + 2 * s + 1] * g->dt / 3.0;
-        }
-    }
-    return BFVM_OK;
+    return bfvm::adjoint_step_into(g, field_in, grad, g->work, g->red_partials, g->red_out, grad_D, grad_lambda);
 }
 
 int bfvm_device_bytes(bfvm_grid g, int64_t* bytes)

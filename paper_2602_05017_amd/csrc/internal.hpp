@@ -106,6 +106,16 @@ hipError_t launch_fill_gaussian(int dtype, void* u, int64_t nx, int64_t ny, int6
 
 }  // namespace bfvm
 
+struct bfvm_grid_s;
+
+namespace bfvm {
+// One reverse step (bfvm_step_adjoint) into caller-provided workspace, shared
+// by the allocating and the allocation-free entry points (grid.cpp).
+int64_t adjoint_partials_count(bfvm_grid_s* g);
+int adjoint_step_into(bfvm_grid_s* g, const void* field_in, void* grad, void* const work[3], double* partials,
+                      double* red_out, double* grad_D, double* grad_lambda);
+}  // namespace bfvm
+
 // --------------------------------------------------------------- grid object
 struct bfvm_grid_s {
     int64_t nx = 0, ny = 0, nz = 0;
