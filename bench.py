@@ -399,9 +399,9 @@ def run_batch(args):
 
 # algorithmic bytes per element of one reverse step without sources and
 # Dirichlet entries, in units of the element size: three recomputed sweeps
-# (6, the first reading the state itself), three transposed sweeps (6),
-# three reductions reading the gradient and the sweep output (6)
-ADJOINT_ELEMS_MOVED = 18
+# (6, the first reading the state itself) and three transposed sweeps that
+# also read the recomputed output to form the parameter sums (9)
+ADJOINT_ELEMS_MOVED = 15
 
 
 def run_adjoint(args):
@@ -455,6 +455,33 @@ def run_adjoint(args):
         log(f"adjoint {dtype}: reverse step {1e3 * t_rev:.3f} ms ({alg / t_rev / 1e9:.0f} GB/s algorithmic), "
             f"50-step forward {1e3 * t_fwd:.1f} ms, backward {1e3 * t_bwd:.1f} ms")
         g.close()
+    # the reverse step where it is bound by HBM: 512^3 x 4 in FP64 (4.3 GB per
+    # field; state, gradient and the three recomputed sweep outputs resident)
+    q = workloads.config(4, n=512, nsub=4, with_field=False)
+    gq = make_grid(q, "f64")
+    uq = torch.empty(q.shape, dtype=torch.float64, device="cuda")
+    gradq = torch.empty_like(uq)
+    gq.fill_uniform(uq, q.seed, 0)
+    gq.fill_uniform(gradq, q.seed, 4, -0.5, 0.5)
+    gq.step_adjoint(uq, gradq)
+    torch.cuda.synchronize()
+    reps_q = 5
+    t0 = time.perf_counter()
+    for _ in range(reps_q):
+        gq.step_adjoint(uq, gradq)
+    torch.cuda.synchronize()
+    tq = (time.perf_counter() - t0) / reps_q
+    upd_q = q.V * q.S
+    alg_q = ADJOINT_ELEMS_MOVED * 8 * upd_q
+    hbm_bound = {"grid": [q.nx, q.ny, q.nz], "substrates": q.S, "dtype": "f64",
+                 "ms_per_reverse_step": round(1e3 * tq, 3), "reverse_updates_per_s": upd_q / tq,
+                 "algorithmic_bytes": alg_q, "alg_GBps": round(alg_q / tq / 1e9, 1),
+                 "frac": round(alg_q / tq / 1e9 / HBM_PEAK_GBPS, 4)}
+    log(f"reverse step on 512^3 x 4 FP64: {1e3 * tq:.2f} ms, {alg_q / tq / 1e9:.0f} GB/s algorithmic "
+        f"({ADJOINT_ELEMS_MOVED} element moves per voxel-substrate)")
+    gq.close()
+    del uq, gradq
+    torch.cuda.empty_cache()
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -478,10 +505,11 @@ def run_adjoint(args):
                    "grid": [p.nx, p.ny, p.nz], "substrates": p.S},
         "roofline": {"bound": "hbm", "achieved": r64["reverse_step_alg_GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(r64["reverse_step_alg_GBps"] / HBM_PEAK_GBPS, 4), "traffic": None,
-                     "scope": "whole reverse step: 20 element moves per voxel-substrate / step time; the 34 MB "
+                     "scope": "whole reverse step: 15 element moves per voxel-substrate / step time; the 34 MB "
                               "field fits the 256 MB memory-side cache, so this can exceed HBM bandwidth",
                      "algorithmic_bytes_per_step": ADJOINT_ELEMS_MOVED * 8 * upd},
         "adjoint": out,
+        "reverse_step_hbm_bound": hbm_bound,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

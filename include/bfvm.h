@@ -130,8 +130,10 @@ int bfvm_sweep(bfvm_grid g, void* field, int32_t axis);
  * then runs Dir^T, Z^T, Dir^T, Y^T, Dir^T, X^T, Dir^T, Src^T, where each
  * sweep transpose is a transposed Thomas solve (A = L U, solve U^T then L^T),
  * and accumulates per substrate -y^T (L_N x) (w.r.t. r) and -y^T x (w.r.t.
- * beta) with L_N the zero-flux Laplacian, in a fixed-order two-stage
- * reduction (deterministic).  Synchronises the stream before returning.
+ * beta) with L_N the zero-flux Laplacian: each transposed sweep forms the
+ * sums of its lines from the y it holds and the recomputed x, then one
+ * launch adds the lines of each substrate in a fixed order (deterministic).
+ * Synchronises the stream before returning.
  * Errors: EINVAL, ESTATE, ENOMEM, EDEVICE. */
 int bfvm_step_adjoint(bfvm_grid g, const void* field_in, void* grad,
                       double* grad_D, double* grad_lambda);
@@ -140,14 +142,14 @@ int bfvm_step_adjoint(bfvm_grid g, const void* field_in, void* grad,
  * under graph capture, tight serving loops, harnesses that forbid
  * hipMalloc.  Same arguments, results and synchronisation as
  * bfvm_step_adjoint, and the same kernels; the workspace (three sweep
- * outputs, reduction partials and results) comes from a device array of
- * 97 MiB that the library's code object carries (each GPU the library
- * runs on holds one copy until the process ends) instead of allocations.
- * The call allocates no device memory, and no host memory except to
- * format an error message.  Limit: 3 * (field bytes,
- * rounded up to 256) + the reduction partials (48 KiB per substrate) +
- * 48 B per substrate must fit in 97 MiB; the 128^3 x 2 FP64 grid does
- * (e.g. 96 MiB of sweep outputs).  Every call on one GPU shares that GPU's
+ * outputs, per-line sums, results) comes from a device array of 98 MiB
+ * that the library's code object carries (each GPU the library runs on
+ * holds one copy until the process ends) instead of allocations.  The call
+ * allocates no device memory, and no host memory except to format an error
+ * message.  Limit: 3 * (field bytes, rounded up to 256) + 16 bytes per line
+ * of each axis (nelem/nx + nelem/ny + nelem/nz lines) + 48 bytes per
+ * substrate must fit in 98 MiB; the 128^3 x 2 FP64 grid does (96 MiB of
+ * sweep outputs, 1.5 MiB of sums).  Every call on one GPU shares that GPU's
  * array: calls that overlap on one GPU (several threads or streams) race.
  * Errors: EINVAL (NULL pointers, grid too large: nothing is enqueued),
  * ESTATE, EDEVICE. */

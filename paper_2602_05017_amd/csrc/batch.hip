@@ -4,7 +4,8 @@
 //
 // Each domain's step is a linear chain of stages (source, Dirichlet, x sweep,
 // Dirichlet, y sweep, Dirichlet, z sweep, Dirichlet; the adjoint step adds
-// copies, transposed sweeps, masks, reductions).  Every stage is cut into
+// copies, masks and transposed sweeps that also form the parameter sums).
+// Every stage is cut into
 // work items (tiles of lines for sweeps, ranges for the sparse stages).
 //
 // Grouped mode (the default): one kernel launch per stage covers that stage
@@ -48,7 +49,6 @@ enum StageType : int32_t {
     ST_MASK = 4,     // g <- 0 at Dirichlet entries
     ST_SRC_T = 5,    // g <- g * invQ at source entries
     ST_COPY = 6,     // buffer out <- buffer in
-    ST_REDUCE = 7,   // per-substrate sums of y (L_N x) and y x along axis
 };
 
 constexpr int kBatchThreads = 512;
@@ -57,6 +57,9 @@ constexpr int kBatchTab = 2048;   // line length x substrates, per axis
 // elements per thread M in {4, 8} and at most 512/16 = 32 segments per line
 constexpr int64_t kMaxBatchLine = 256;
 constexpr int kNumBuf = 5;   // 0 field, 1 gradient, 2..4 adjoint workspace
+// substrates per domain: the reverse step's per-substrate sums of an item
+// are kept in LDS
+constexpr int kMaxBatchSub = 256;
 
 struct BDomain {
     int32_t dtype;
@@ -81,12 +84,13 @@ struct BItem {
     int32_t type;
     int32_t axis;
     int32_t in, out;
+    int32_t xb;        // SWEEP_T: buffer of the forward output x for the parameter sums
     int32_t done;      // counter incremented when the item completes
     int32_t dep;       // counter to wait for (-1: none)
     uint32_t need;     // value of counter dep that means "stage complete"
     int32_t m, lpw;    // sweeps: elements per thread and lines per tile
     int64_t a0, a1;    // range (tiles, entries, elements or voxels)
-    int64_t slot;      // REDUCE: offset of the item's 2*S partial sums
+    int64_t slot;      // SWEEP_T: offset of the item's 2*S parameter sums
 };
 
 // ------------------------------------------------------------ device work
@@ -159,7 +163,7 @@ __device__ __forceinline__ void tile_load(const T* in, const TileSpot& t, int st
 template <typename T, typename C, int M, bool TR>
 __device__ __forceinline__ void tile_solve_store(T* out, const TileSpot& t, int st, const T (&raw)[M], int S,
                                                  int lpw, const C* __restrict__ invd, const C* __restrict__ rr,
-                                                 C* sc)
+                                                 C* sc, C (&v)[M])
 {
     const int K = blockDim.x / lpw;
     const int lane = threadIdx.x & 63;
@@ -167,7 +171,6 @@ __device__ __forceinline__ void tile_solve_store(T* out, const TileSpot& t, int 
     const int line = lane % lpw;
     const int seg = wave * (64 / lpw) + lane / lpw;
     const int i0 = seg * M;
-    C v[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) v[k] = (C)raw[k];
     const C r = rr[t.s];
@@ -184,37 +187,102 @@ __device__ __forceinline__ void tile_solve_store(T* out, const TileSpot& t, int 
         if (k < t.cnt) op[k * st] = (T)v[k];
 }
 
+// The reverse step's parameter sums of one transposed tile (y in v, the
+// forward output x streamed from xf): per-line sums in segment order, then
+// added into acc[2 s], acc[2 s + 1] by substrate in line order.  Every
+// thread of the block calls this; lsum holds 2 doubles per line of the tile.
+template <typename T, typename C, int M>
+__device__ __forceinline__ void tile_sums(const C (&v)[M], const TileSpot& t, const SweepShape& q, int S, int lpw,
+                                          int64_t ox, const T* __restrict__ xf, C* sc, double* lsum, double* acc)
+{
+    const int K = blockDim.x / lpw;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int line = lane % lpw;
+    const int seg = wave * (64 / lpw) + lane / lpw;
+    double a0 = 0.0, a1 = 0.0;
+    if (t.cnt > 0) seg_adjoint_sums<C, M, false>(v, xf + t.base, (int64_t)q.stride, t.last, seg > 0, a0, a1);
+    const int KP = scan_kp(K, lpw, (int)blockDim.x, true);
+    const int A = KP ? lpw * (KP + 1) : K * lpw;
+    double* s0 = reinterpret_cast<double*>(sc);
+    double* s1 = s0 + A;
+    __syncthreads();   // the solve's last reads of the carry arrays are done
+    const int slot = KP ? line * (KP + 1) + seg : seg * lpw + line;
+    s0[slot] = a0;
+    s1[slot] = a1;
+    __syncthreads();
+    const int64_t p0 = ox * lpw;
+    const int nvalid = (int)min((int64_t)lpw, q.inner - p0);
+    const int l = (int)threadIdx.x;
+    if (l < nvalid) {
+        double b0 = 0.0, b1 = 0.0;
+        for (int j = 0; j < K; ++j) {
+            const int sl = KP ? l * (KP + 1) + j : j * lpw + l;
+            b0 += s0[sl];
+            b1 += s1[sl];
+        }
+        lsum[2 * l + 0] = b0;
+        lsum[2 * l + 1] = b1;
+    }
+    __syncthreads();
+    // line p0 + l belongs to substrate (p0 + l) % S
+    const int ph = (int)(p0 % S);
+    for (int sub = (int)threadIdx.x; sub < S; sub += (int)blockDim.x) {
+        double b0 = acc[2 * sub + 0], b1 = acc[2 * sub + 1];
+        for (int l2 = (sub - ph + S) % S; l2 < nvalid; l2 += S) {
+            b0 += lsum[2 * l2 + 0];
+            b1 += lsum[2 * l2 + 1];
+        }
+        acc[2 * sub + 0] = b0;
+        acc[2 * sub + 1] = b1;
+    }
+}
+
+// One tile; for transposed tiles also the parameter sums (xf, lsum, acc).
 template <typename T, typename C, int M, bool TR>
 __device__ __forceinline__ void batch_tile(const T* in, T* out, const SweepShape& q, int S, int lpw, int64_t ox,
-                                           int64_t oy, const C* __restrict__ invd, const C* __restrict__ rr, C* sc)
+                                           int64_t oy, const C* __restrict__ invd, const C* __restrict__ rr, C* sc,
+                                           const T* __restrict__ xf, double* lsum, double* acc)
 {
     const TileSpot t = tile_spot(q, S, lpw, M, ox, oy);
     T raw[M];
     tile_load<T, M>(in, t, (int)q.stride, raw);
-    tile_solve_store<T, C, M, TR>(out, t, (int)q.stride, raw, S, lpw, invd, rr, sc);
+    C v[M];
+    tile_solve_store<T, C, M, TR>(out, t, (int)q.stride, raw, S, lpw, invd, rr, sc, v);
+    if constexpr (TR) tile_sums<T, C, M>(v, t, q, S, lpw, ox, xf, sc, lsum, acc);
 }
 
+// acc: 2 * S doubles of the item's parameter sums (transposed items)
 template <typename T, typename C, bool TR>
-__device__ void batch_sweep_item(const BDomain& d, const BItem& it, C* sc)
+__device__ void batch_sweep_item(const BDomain& d, const BItem& it, C* sc, double* lsum, double* acc,
+                                 double* partials)
 {
     const SweepShape q = sweep_shape(d, it.axis);
     const int lpw = it.lpw;
     const int64_t tpo = (q.inner + lpw - 1) / lpw;   // tiles per outer index
     const T* in = static_cast<const T*>(d.buf[it.in]);
     T* out = static_cast<T*>(d.buf[it.out]);
+    const T* xf = TR ? static_cast<const T*>(d.buf[it.xb]) : nullptr;
     const C* invd = static_cast<const C*>(d.invd[it.axis]);
     const C* rr = static_cast<const C*>(d.r[it.axis]);
+    if (TR)
+        for (int sub = threadIdx.x; sub < d.S; sub += blockDim.x) acc[2 * sub] = acc[2 * sub + 1] = 0.0;
     for (int64_t t = it.a0; t < it.a1; ++t) {
         const int64_t oy = t / tpo, ox = t - oy * tpo;
         if (it.m == 4)
-            batch_tile<T, C, 4, TR>(in, out, q, d.S, lpw, ox, oy, invd, rr, sc);
+            batch_tile<T, C, 4, TR>(in, out, q, d.S, lpw, ox, oy, invd, rr, sc, xf, lsum, acc);
         else
-            batch_tile<T, C, 8, TR>(in, out, q, d.S, lpw, ox, oy, invd, rr, sc);
+            batch_tile<T, C, 8, TR>(in, out, q, d.S, lpw, ox, oy, invd, rr, sc, xf, lsum, acc);
     }
+    if (TR)
+        for (int sub = threadIdx.x; sub < d.S; sub += blockDim.x) {
+            partials[it.slot + 2 * sub + 0] = acc[2 * sub + 0];
+            partials[it.slot + 2 * sub + 1] = acc[2 * sub + 1];
+        }
 }
 
 template <typename T>
-__device__ void batch_sparse_item(const BDomain& d, const BItem& it, double* partials, double* red)
+__device__ void batch_sparse_item(const BDomain& d, const BItem& it)
 {
     const int S = d.S;
     switch (it.type) {
@@ -253,92 +321,6 @@ __device__ void batch_sparse_item(const BDomain& d, const BItem& it, double* par
             for (int64_t t = it.a0 + threadIdx.x; t < it.a1; t += blockDim.x) b[t] = a[t];
             break;
         }
-        case ST_REDUCE: {
-            // y = buffer in (gradient after the transposed sweep), x = buffer
-            // out (the forward sweep's output); sums over voxels [a0, a1)
-            const T* y = static_cast<const T*>(d.buf[it.in]);
-            const T* x = static_cast<const T*>(d.buf[it.out]);
-            const SweepShape q = sweep_shape(d, it.axis);
-            const int64_t vstride = it.axis == 0 ? 1 : (it.axis == 1 ? d.nx : d.nx * d.ny);
-            const int64_t est = vstride * S;
-            // (v / vstride) % n through FP64 reciprocals: (w + 1/2) / d lies at
-            // least 1/(2d) from an integer and errs by less than 2^-20 / d for
-            // w < 2^31, so truncation is exact
-            const double inv_vs = 1.0 / (double)vstride, inv_n = 1.0 / (double)q.n;
-            if (2 * S <= (int)blockDim.x) {
-                // One pass over the item's elements for all substrates: thread t
-                // takes the elements t, t + L, t + 2L, ... of [a0 S, a1 S) with
-                // L = S * P, P = blockDim / S rows of S threads, so its substrate
-                // t % S never changes (threads from L on idle).  Then one
-                // fixed-order tree over the P rows: deterministic.
-                const int t = threadIdx.x, P = (int)blockDim.x / S, L = P * S;
-                const int sub = t % S, row = t / S;
-                double a0 = 0.0, a1 = 0.0;
-                if (t < L) {
-                    for (int64_t v = it.a0 + row; v < it.a1; v += P) {
-                        const int64_t qv = (int64_t)(((double)v + 0.5) * inv_vs);
-                        const int64_t i = qv - (int64_t)(((double)qv + 0.5) * inv_n) * q.n;
-                        const int64_t e = v * S + sub;
-                        const double xe = (double)x[e];
-                        double lx = 0.0;
-                        if (i > 0) lx += xe - (double)x[e - est];
-                        if (i < q.n - 1) lx += xe - (double)x[e + est];
-                        const double ye = (double)y[e];
-                        a0 += ye * lx;
-                        a1 += ye * xe;
-                    }
-                }
-                red[t] = a0;
-                red[blockDim.x + t] = a1;
-                __syncthreads();
-                int w0 = 1;
-                while (w0 < P) w0 <<= 1;
-                for (int w = w0 / 2; w > 0; w >>= 1) {
-                    if (t < L && row < w && row + w < P) {
-                        red[t] += red[t + w * S];
-                        red[blockDim.x + t] += red[blockDim.x + t + w * S];
-                    }
-                    __syncthreads();
-                }
-                if (t < S) {
-                    partials[it.slot + 2 * t + 0] = red[t];
-                    partials[it.slot + 2 * t + 1] = red[blockDim.x + t];
-                }
-                __syncthreads();
-                break;
-            }
-            for (int s = 0; s < S; ++s) {
-                double a0 = 0.0, a1 = 0.0;
-                for (int64_t v = it.a0 + threadIdx.x; v < it.a1; v += blockDim.x) {
-                    const int64_t qv = (int64_t)(((double)v + 0.5) * inv_vs);
-                    const int64_t i = qv - (int64_t)(((double)qv + 0.5) * inv_n) * q.n;
-                    const int64_t e = v * S + s;
-                    const double xe = (double)x[e];
-                    double lx = 0.0;
-                    if (i > 0) lx += xe - (double)x[e - est];
-                    if (i < q.n - 1) lx += xe - (double)x[e + est];
-                    const double ye = (double)y[e];
-                    a0 += ye * lx;
-                    a1 += ye * xe;
-                }
-                red[threadIdx.x] = a0;
-                red[blockDim.x + threadIdx.x] = a1;
-                __syncthreads();
-                for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-                    if ((int)threadIdx.x < w) {
-                        red[threadIdx.x] += red[threadIdx.x + w];
-                        red[blockDim.x + threadIdx.x] += red[blockDim.x + threadIdx.x + w];
-                    }
-                    __syncthreads();
-                }
-                if (threadIdx.x == 0) {
-                    partials[it.slot + 2 * s + 0] = red[0];
-                    partials[it.slot + 2 * s + 1] = red[blockDim.x];
-                }
-                __syncthreads();
-            }
-            break;
-        }
         default: break;
     }
 }
@@ -356,13 +338,19 @@ __device__ void batch_sparse_item(const BDomain& d, const BItem& it, double* par
 // domains: the forward M = 16 tiles at 128 VGPRs (a few spilled) instead of
 // 136 took the step from 5.21 to 4.78 ms; the transposed ones (45 spilled)
 // made the reverse step 8% slower, so they keep one block per CU.
+// Transposed items also form the reverse step's parameter sums of their
+// tiles from the y they hold and the forward output x (buffer it.xb), and
+// write the item's 2 S sums to partials[it.slot].
 template <typename T, typename C, int M, bool TR>
 __global__ __launch_bounds__(kBatchThreads, (TR && M > 8) ? 2 : 4) void k_group_sweep(const BDomain* __restrict__ doms,
-                                                                                      const BItem* __restrict__ items)
+                                                                                      const BItem* __restrict__ items,
+                                                                                      double* __restrict__ partials)
 {
     // carry arrays, lane-parallel layout: lpw * (K + 1) = 512 + lpw <= 576 slots each
     __shared__ __align__(16) C sc[4 * (kBatchThreads + 64)];
     __shared__ __align__(16) C tab[kBatchTab];
+    __shared__ double lsum[TR ? 2 * 64 : 1];
+    __shared__ double acc[TR ? 2 * kMaxBatchSub : 1];
     const BItem it = items[blockIdx.x];
     const BDomain& d = doms[it.dom];
     const SweepShape q = sweep_shape(d, it.axis);
@@ -370,27 +358,34 @@ __global__ __launch_bounds__(kBatchThreads, (TR && M > 8) ? 2 : 4) void k_group_
     const int64_t tpo = (q.inner + lpw - 1) / lpw;   // tiles per outer index
     const T* in = static_cast<const T*>(d.buf[it.in]);
     T* out = static_cast<T*>(d.buf[it.out]);
+    const T* xf = TR ? static_cast<const T*>(d.buf[it.xb]) : nullptr;
     const C* invd = static_cast<const C*>(d.invd[it.axis]);
     const C* rr = static_cast<const C*>(d.r[it.axis]);
     const int nS = (int)(q.n * d.S);   // <= kBatchTab (checked when the batch is created)
     for (int e = threadIdx.x; e < nS; e += blockDim.x) tab[e] = invd[e];
+    if (TR)
+        for (int sub = threadIdx.x; sub < d.S; sub += blockDim.x) acc[2 * sub] = acc[2 * sub + 1] = 0.0;
     __syncthreads();
     for (int64_t t = it.a0; t < it.a1; ++t) {
         const int64_t oy = t / tpo, ox = t - oy * tpo;
-        batch_tile<T, C, M, TR>(in, out, q, d.S, lpw, ox, oy, tab, rr, sc);
+        batch_tile<T, C, M, TR>(in, out, q, d.S, lpw, ox, oy, tab, rr, sc, xf, lsum, acc);
     }
+    if (TR)
+        for (int sub = threadIdx.x; sub < d.S; sub += blockDim.x) {
+            partials[it.slot + 2 * sub + 0] = acc[2 * sub + 0];
+            partials[it.slot + 2 * sub + 1] = acc[2 * sub + 1];
+        }
 }
 
-// One block per item of one sparse stage (source, Dirichlet, mask, copy,
-// reduction) of one storage type.
+// One block per item of one sparse stage (source, Dirichlet, mask, copy) of
+// one storage type.
 __global__ __launch_bounds__(kBatchThreads) void k_group_sparse(const BDomain* __restrict__ doms,
-                                                                const BItem* __restrict__ items, double* partials)
+                                                                const BItem* __restrict__ items)
 {
-    __shared__ double red[2 * kBatchThreads];
     const BItem it = items[blockIdx.x];
     const BDomain& d = doms[it.dom];
-    if (d.dtype == DT_F64) batch_sparse_item<double>(d, it, partials, red);
-    else batch_sparse_item<float>(d, it, partials, red);
+    if (d.dtype == DT_F64) batch_sparse_item<double>(d, it);
+    else batch_sparse_item<float>(d, it);
 }
 
 // ------------------------------------------------- persistent mode (off)
@@ -410,7 +405,9 @@ __global__ __launch_bounds__(kBatchThreads, 4) void k_batch(const BDomain* __res
                                                          uint32_t* counters, double* partials,
                                                          uint64_t limit_ticks)
 {
-    __shared__ __align__(16) double sc[4 * (kBatchThreads + 64)];   // carry arrays (also the reduction buffer)
+    __shared__ __align__(16) double sc[4 * (kBatchThreads + 64)];   // carry arrays
+    __shared__ double lsum[2 * 64];
+    __shared__ double acc[2 * kMaxBatchSub];
     __shared__ int64_t s_item;
     uint32_t* head = counters;
     uint32_t* err = counters + 1;
@@ -446,19 +443,19 @@ __global__ __launch_bounds__(kBatchThreads, 4) void k_batch(const BDomain* __res
         if (it.type == ST_SWEEP || it.type == ST_SWEEP_T) {
             const bool tr = it.type == ST_SWEEP_T;
             if (d.dtype == DT_F64) {
-                if (tr) batch_sweep_item<double, double, true>(d, it, sc);
-                else batch_sweep_item<double, double, false>(d, it, sc);
+                if (tr) batch_sweep_item<double, double, true>(d, it, sc, lsum, acc, partials);
+                else batch_sweep_item<double, double, false>(d, it, sc, lsum, acc, partials);
             } else if (d.dtype == DT_F32) {
-                if (tr) batch_sweep_item<float, double, true>(d, it, sc);
-                else batch_sweep_item<float, double, false>(d, it, sc);
+                if (tr) batch_sweep_item<float, double, true>(d, it, sc, lsum, acc, partials);
+                else batch_sweep_item<float, double, false>(d, it, sc, lsum, acc, partials);
             } else {
                 float* scf = reinterpret_cast<float*>(sc);
-                if (tr) batch_sweep_item<float, float, true>(d, it, scf);
-                else batch_sweep_item<float, float, false>(d, it, scf);
+                if (tr) batch_sweep_item<float, float, true>(d, it, scf, lsum, acc, partials);
+                else batch_sweep_item<float, float, false>(d, it, scf, lsum, acc, partials);
             }
         } else {
-            if (d.dtype == DT_F64) batch_sparse_item<double>(d, it, partials, sc);
-            else batch_sparse_item<float>(d, it, partials, sc);
+            if (d.dtype == DT_F64) batch_sparse_item<double>(d, it);
+            else batch_sparse_item<float>(d, it);
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -497,6 +494,7 @@ constexpr bool kPersistentModeEnabled = false;
 
 struct Stage {
     int32_t type, axis, in, out;
+    int32_t xb = -1;   // SWEEP_T: buffer of the forward output for the parameter sums
 };
 
 // One kernel launch of the grouped mode: the items [off, off + count) of one
@@ -655,7 +653,6 @@ void build_program(bfvm_batch b, const std::vector<int32_t>& which, const std::v
                     total = (d.ndir == 0 && (sg.in != 0 || d.nsrc == 0)) ? 0 : nel;
                     chunk = b->chunk_elems;
                     break;
-                case ST_REDUCE: total = d.nx * d.ny * d.nz; chunk = std::max<int64_t>(1, b->chunk_elems / d.S); break;
                 default: {
                     total = tiles_of(d, sg.axis, tl);
                     const int64_t per_tile = (int64_t)tl * axis_len(d, sg.axis);
@@ -669,6 +666,7 @@ void build_program(bfvm_batch b, const std::vector<int32_t>& which, const std::v
                 it.axis = sg.axis;
                 it.in = sg.in;
                 it.out = sg.out;
+                it.xb = sg.xb;
                 it.m = tm;
                 it.lpw = tl;
                 if (sg.type == ST_SWEEP && sg.in == sg.out && sg.in >= 2 && d.ndir == 0) {
@@ -677,7 +675,7 @@ void build_program(bfvm_batch b, const std::vector<int32_t>& which, const std::v
                 }
                 it.a0 = a0;
                 it.a1 = std::min(total, a0 + chunk);
-                if (sg.type == ST_REDUCE) {
+                if (sg.type == ST_SWEEP_T) {
                     it.slot = partials;
                     partials += 2 * d.S;
                 }
@@ -743,20 +741,21 @@ std::vector<Stage> forward_program()
 }
 
 // adjoint of one step: recompute the sweep outputs into buffers 2, 3, 4 from
-// the state in buffer 0, then run the transposed stages on the gradient (1).
-// Written for domains with Dirichlet entries (each sweep runs on an
-// overwritten copy, so the previous sweep's output stays intact for its
-// reduction); build_program drops the two inner copies of a domain without
-// Dirichlet entries and runs its y and z sweeps 2 -> 3 and 3 -> 4; without
-// sources either, it also drops the first copy and runs the x sweep 0 -> 2.
+// the state in buffer 0, then run the transposed stages on the gradient (1);
+// each transposed sweep also forms its axis's parameter sums from the
+// forward output of that axis (buffer 4, 3, 2 for z, y, x).  Written for
+// domains with Dirichlet entries (each sweep runs on an overwritten copy, so
+// the previous sweep's output stays intact for the sums); build_program
+// drops the two inner copies of a domain without Dirichlet entries and runs
+// its y and z sweeps 2 -> 3 and 3 -> 4; without sources either, it also
+// drops the first copy and runs the x sweep 0 -> 2.
 std::vector<Stage> adjoint_program()
 {
-    return {{ST_COPY, 0, 0, 2},    {ST_SRC, 0, 2, 2},     {ST_DIR, 0, 2, 2},   {ST_SWEEP, 0, 2, 2},
-            {ST_COPY, 0, 2, 3},    {ST_DIR, 0, 3, 3},     {ST_SWEEP, 1, 3, 3}, {ST_COPY, 0, 3, 4},
-            {ST_DIR, 0, 4, 4},     {ST_SWEEP, 2, 4, 4},   {ST_MASK, 0, 1, 1},  {ST_SWEEP_T, 2, 1, 1},
-            {ST_REDUCE, 2, 1, 4},  {ST_MASK, 0, 1, 1},    {ST_SWEEP_T, 1, 1, 1}, {ST_REDUCE, 1, 1, 3},
-            {ST_MASK, 0, 1, 1},    {ST_SWEEP_T, 0, 1, 1}, {ST_REDUCE, 0, 1, 2}, {ST_MASK, 0, 1, 1},
-            {ST_SRC_T, 0, 1, 1}};
+    return {{ST_COPY, 0, 0, 2},       {ST_SRC, 0, 2, 2},    {ST_DIR, 0, 2, 2},          {ST_SWEEP, 0, 2, 2},
+            {ST_COPY, 0, 2, 3},       {ST_DIR, 0, 3, 3},    {ST_SWEEP, 1, 3, 3},        {ST_COPY, 0, 3, 4},
+            {ST_DIR, 0, 4, 4},        {ST_SWEEP, 2, 4, 4},  {ST_MASK, 0, 1, 1},         {ST_SWEEP_T, 2, 1, 1, 4},
+            {ST_MASK, 0, 1, 1},       {ST_SWEEP_T, 1, 1, 1, 3}, {ST_MASK, 0, 1, 1},     {ST_SWEEP_T, 0, 1, 1, 2},
+            {ST_MASK, 0, 1, 1},       {ST_SRC_T, 0, 1, 1}};
 }
 
 // Counters that blocks of one launch use to hand work to each other must be
@@ -832,13 +831,13 @@ int build_forward(bfvm_batch b)
 }
 
 template <typename T, typename C, bool TR>
-void launch_group_sweep(int M, int64_t n, hipStream_t s, const BDomain* d, const BItem* it)
+void launch_group_sweep(int M, int64_t n, hipStream_t s, const BDomain* d, const BItem* it, double* partials)
 {
     const dim3 grid((unsigned)n), block(kBatchThreads);
     switch (M) {
-        case 4: hipLaunchKernelGGL((k_group_sweep<T, C, 4, TR>), grid, block, 0, s, d, it); break;
-        case 8: hipLaunchKernelGGL((k_group_sweep<T, C, 8, TR>), grid, block, 0, s, d, it); break;
-        default: hipLaunchKernelGGL((k_group_sweep<T, C, 16, TR>), grid, block, 0, s, d, it); break;
+        case 4: hipLaunchKernelGGL((k_group_sweep<T, C, 4, TR>), grid, block, 0, s, d, it, partials); break;
+        case 8: hipLaunchKernelGGL((k_group_sweep<T, C, 8, TR>), grid, block, 0, s, d, it, partials); break;
+        default: hipLaunchKernelGGL((k_group_sweep<T, C, 16, TR>), grid, block, 0, s, d, it, partials); break;
     }
 }
 
@@ -873,18 +872,18 @@ int enqueue_program(bfvm_batch b, const Program& P)
     for (const Launch& L : P.launches) {
         const BItem* it = P.d_items + L.off;
         const hipStream_t s = cs[chain_of[L.dtype]];
+        double* pt = b->d_partials;
         if (!L.sweep) {
-            hipLaunchKernelGGL(k_group_sparse, dim3((unsigned)L.count), dim3(kBatchThreads), 0, s, b->d_doms, it,
-                               b->d_partials);
+            hipLaunchKernelGGL(k_group_sparse, dim3((unsigned)L.count), dim3(kBatchThreads), 0, s, b->d_doms, it);
         } else if (L.dtype == BFVM_F64) {
-            if (L.tr) launch_group_sweep<double, double, true>(L.M, L.count, s, b->d_doms, it);
-            else launch_group_sweep<double, double, false>(L.M, L.count, s, b->d_doms, it);
+            if (L.tr) launch_group_sweep<double, double, true>(L.M, L.count, s, b->d_doms, it, pt);
+            else launch_group_sweep<double, double, false>(L.M, L.count, s, b->d_doms, it, pt);
         } else if (L.dtype == BFVM_F32) {
-            if (L.tr) launch_group_sweep<float, double, true>(L.M, L.count, s, b->d_doms, it);
-            else launch_group_sweep<float, double, false>(L.M, L.count, s, b->d_doms, it);
+            if (L.tr) launch_group_sweep<float, double, true>(L.M, L.count, s, b->d_doms, it, pt);
+            else launch_group_sweep<float, double, false>(L.M, L.count, s, b->d_doms, it, pt);
         } else {
-            if (L.tr) launch_group_sweep<float, float, true>(L.M, L.count, s, b->d_doms, it);
-            else launch_group_sweep<float, float, false>(L.M, L.count, s, b->d_doms, it);
+            if (L.tr) launch_group_sweep<float, float, true>(L.M, L.count, s, b->d_doms, it, pt);
+            else launch_group_sweep<float, float, false>(L.M, L.count, s, b->d_doms, it, pt);
         }
         BHIP(hipGetLastError(), "grouped stage kernel");
     }
@@ -989,6 +988,7 @@ int bfvm_batch_create(bfvm_batch* out, int32_t ndomains, const bfvm_grid* grids,
             if (n * grids[i]->S > kBatchTab)
                 return bfail(BFVM_EINVAL, "batched domains support line length x substrates up to 2048");
         }
+        if (grids[i]->S > kMaxBatchSub) return bfail(BFVM_EINVAL, "batched domains support up to 256 substrates");
         // (implied by the two limits above: the kernels use 32-bit element offsets)
         if (grids[i]->nelem() >= (1ll << 31)) return bfail(BFVM_EINVAL, "batched domain too large");
     }
@@ -1177,7 +1177,7 @@ int bfvm_batch_step_adjoint(bfvm_batch b, int32_t count, const int32_t* subset, 
     }
     std::vector<double> Gr(base * 3, 0.0), Gb(base * 3, 0.0);
     for (const BItem& it : b->adj.items) {
-        if (it.type != ST_REDUCE) continue;
+        if (it.type != ST_SWEEP_T) continue;
         const int i = pos[it.dom];
         const int S = b->doms[it.dom].S;
         for (int s = 0; s < S; ++s) {

@@ -202,7 +202,8 @@ int run_dirichlet(bfvm_grid g, void* u)
     return e == hipSuccess ? BFVM_OK : hip_fail(e, "dirichlet kernel");
 }
 
-int run_sweep_geo(bfvm_grid g, int axis, const AxisGeom& geo, const void* in, void* out, bool transposed)
+int run_sweep_geo(bfvm_grid g, int axis, const AxisGeom& geo, const void* in, void* out, bool transposed,
+                  const AdjSums& red = AdjSums())
 {
     const bool f32c = g->dtype == BFVM_F32_FAST;
     const void* invd = f32c ? (const void*)g->invd32[axis] : (const void*)g->invd64[axis];
@@ -211,14 +212,14 @@ int run_sweep_geo(bfvm_grid g, int axis, const AxisGeom& geo, const void* in, vo
     hipEvent_t a;
     time_begin(g, 2 + axis, &a);
     hipError_t e = launch_sweep(g->dtype, transposed, g->plan[axis], geo, in, out, invd, r, comp, g->comp_H[axis],
-                                g->stream);
+                                g->stream, red);
     time_end(g, 2 + axis, a, geo.n * geo.inner * geo.outer);
     return e == hipSuccess ? BFVM_OK : hip_fail(e, "sweep kernel");
 }
 
-int run_sweep(bfvm_grid g, int axis, const void* in, void* out, bool transposed)
+int run_sweep(bfvm_grid g, int axis, const void* in, void* out, bool transposed, const AdjSums& red = AdjSums())
 {
-    return run_sweep_geo(g, axis, axis_geom(axis, g->nx, g->ny, g->nz, g->S), in, out, transposed);
+    return run_sweep_geo(g, axis, axis_geom(axis, g->nx, g->ny, g->nz, g->S), in, out, transposed, red);
 }
 
 // ------------------------------------------------------- fused schedules
@@ -372,7 +373,13 @@ int check_grid(bfvm_grid g)
 
 namespace bfvm {
 
-int64_t adjoint_partials_count(bfvm_grid g) { return 3 * 2 * (int64_t)g->S * adjoint_reduce_blocks(g->nvox()); }
+// per-line sums of the three axes: 2 doubles per line, axis by axis
+int64_t adjoint_partials_count(bfvm_grid g)
+{
+    int64_t n = 0;
+    for (int a = 0; a < 3; ++a) n += 2 * axis_lines(axis_geom(a, g->nx, g->ny, g->nz, g->S));
+    return n;
+}
 
 // One reverse step into caller-provided workspace: work[3] field buffers,
 // partials (adjoint_partials_count doubles), red_out (6 S doubles).
@@ -384,7 +391,6 @@ int adjoint_step_into(bfvm_grid g, const void* field_in, void* grad, void* const
 {
     const size_t bytes = (size_t)g->nelem() * dtype_size(g->dtype);
     const int S = g->S;
-    const int64_t nb = adjoint_reduce_blocks(g->nvox());
     hipStream_t st = g->stream;
     int rc;
     // forward recomputation: work[a] = output of sweep a (before the following
@@ -410,16 +416,26 @@ int adjoint_step_into(bfvm_grid g, const void* field_in, void* grad, void* const
             return rc;
         }
     }
-    // reverse: Dir^T, Z^T, Dir^T, Y^T, Dir^T, X^T, Dir^T, Src^T
+    // reverse: Dir^T, Z^T, Dir^T, Y^T, Dir^T, X^T, Dir^T, Src^T.  Each
+    // transposed sweep also forms its per-line sums of y^T (L_N x) and y^T x
+    // from the y it holds and the forward output x = work[a].
+    double* part[3];
+    int64_t nlines[3];
+    int64_t off = 0;
+    for (int a = 0; a < 3; ++a) {
+        part[a] = partials + off;
+        nlines[a] = axis_lines(axis_geom(a, g->nx, g->ny, g->nz, S));
+        off += 2 * nlines[a];
+    }
     for (int a = 2; a >= 0; --a) {
         hipError_t e = launch_mask(g->dtype, grad, g->dir_elem, g->ndir, st);
         if (e != hipSuccess) return hip_fail(e, "mask kernel");
-        if ((rc = run_sweep(g, a, grad, grad, true))) return rc;
-        const AxisGeom geo = axis_geom(a, g->nx, g->ny, g->nz, S);
-        e = launch_adjoint_partials(g->dtype, grad, work[a], geo, g->nelem(), partials + a * 2 * S * nb, nb, st);
-        if (e != hipSuccess) return hip_fail(e, "adjoint reduction");
+        AdjSums red;
+        red.x = work[a];
+        red.part = part[a];
+        if ((rc = run_sweep(g, a, grad, grad, true, red))) return rc;
     }
-    hipError_t ef = launch_adjoint_final(partials, nb, S, 3, red_out, st);
+    hipError_t ef = launch_adjoint_line_final(part, nlines, S, red_out, st);
     if (ef != hipSuccess) return hip_fail(ef, "adjoint reduction");
     hipError_t e = launch_mask(g->dtype, grad, g->dir_elem, g->ndir, st);
     if (e != hipSuccess) return hip_fail(e, "mask kernel");
@@ -729,12 +745,12 @@ int bfvm_step_adjoint(bfvm_grid g, const void* field_in, void* grad, double* gra
             }
         }
     }
-    // partials of the three axes side by side, summed by one final launch
-    const int64_t nb = adjoint_reduce_blocks(g->nvox());
-    if (!g->red_partials || g->red_blocks < nb) {
+    // per-line sums of the three axes side by side, summed by one final launch
+    const int64_t np = bfvm::adjoint_partials_count(g);
+    if (!g->red_partials || g->red_count < np) {
         dfree(g->red_partials);
-        HIP_TRY(hipMalloc((void**)&g->red_partials, sizeof(double) * 3 * 2 * S * nb), "hipMalloc partials");
-        g->red_blocks = nb;
+        HIP_TRY(hipMalloc((void**)&g->red_partials, sizeof(double) * np), "hipMalloc partials");
+        g->red_count = np;
     }
     if (!g->red_out) HIP_TRY(hipMalloc((void**)&g->red_out, sizeof(double) * 2 * S * 3), "hipMalloc red_out");
     return bfvm::adjoint_step_into(g, field_in, grad, g->work, g->red_partials, g->red_out, grad_D, grad_lambda);

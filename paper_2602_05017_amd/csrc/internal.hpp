@@ -69,13 +69,27 @@ std::string check_plan(const SweepPlan& p, const AxisGeom& g, int dtype);
 // Default plan for an axis.
 SweepPlan default_plan(int axis, const AxisGeom& g, int dtype);
 
+// The reverse step's per-line sums, formed inside a transposed sweep: for
+// line L of the axis, part[2 L] = sum_i y_i (L_N x)_i and part[2 L + 1] =
+// sum_i y_i x_i, with y the sweep's output, x the forward sweep's output on
+// the same lines (field layout) and L_N the zero-flux Laplacian.  Lines are
+// numbered L = o * inner + p (AxisGeom order; for x, row * S + s), so line L
+// belongs to substrate L % S.
+struct AdjSums {
+    const void* x = nullptr;
+    double* part = nullptr;   // nullptr: no sums
+};
+inline int64_t axis_lines(const AxisGeom& g) { return g.inner * g.outer; }
+
 // Enqueue one sweep (forward Thomas, or transposed solve when transposed) of
 // field `in` into `out` (may alias) on `stream`.  coefs point to double or
 // float tables matching the dtype's compute type.
 // comp / comp_H: the axis's exact compressed coefficient table (comp_H < 0: none)
+// red: with red.part set (transposed whole-field sweeps only), also write
+// the per-line sums.
 hipError_t launch_sweep(int dtype, bool transposed, const SweepPlan& plan, const AxisGeom& g,
                         const void* in, void* out, const void* invd, const void* r,
-                        const void* comp, int comp_H, hipStream_t stream);
+                        const void* comp, int comp_H, hipStream_t stream, const AdjSums& red = AdjSums());
 
 // Sparse stages.
 hipError_t launch_source(int dtype, void* u, const int64_t* vox, const double* P,
@@ -96,6 +110,10 @@ hipError_t launch_adjoint_partials(int dtype, const void* y, const void* x, cons
 hipError_t launch_adjoint_final(const double* partials, int64_t nblocks, int S, int naxes, double* out,
                                 hipStream_t stream);
 int64_t adjoint_reduce_blocks(int64_t nvox);
+// Second stage of the per-line sums: out[(a*S + s)*2 + {0,1}] = the sum over
+// the lines L = s (mod S) of axis a (part[a], nlines[a] lines), in line order.
+hipError_t launch_adjoint_line_final(double* const part[3], const int64_t nlines[3], int S, double* out,
+                                     hipStream_t stream);
 
 // Device-side field set-up (fill.hip).
 hipError_t launch_fill_uniform(int dtype, void* u, int64_t n, uint64_t seed, uint32_t stream, double lo, double hi,
@@ -176,8 +194,8 @@ struct bfvm_grid_s {
 
     // adjoint workspace
     void* work[3] = {nullptr, nullptr, nullptr};
-    double* red_partials = nullptr;
-    int64_t red_blocks = 0;
+    double* red_partials = nullptr;   // per-line sums of the reverse step
+    int64_t red_count = 0;            // doubles allocated at red_partials
     double* red_out = nullptr;
 
     // pinned host buffers and events of the .npy field I/O (io.cpp)

@@ -25,8 +25,9 @@
 namespace {
 
 // 96 MiB for the three sweep outputs (the 128^3 x 2 FP64 differentiation
-// grid uses exactly that) plus 1 MiB for partials and results.
-constexpr size_t kScratchBytes = (97ull << 20);
+// grid uses exactly that) plus 2 MiB for the per-line sums (1.5 MiB on that
+// grid) and the results.
+constexpr size_t kScratchBytes = (98ull << 20);
 constexpr size_t kAlign = 256;
 
 __device__ __align__(256) unsigned char scratch[kScratchBytes];

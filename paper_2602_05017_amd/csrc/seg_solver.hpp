@@ -294,6 +294,82 @@ __device__ __forceinline__ void solve_segment(C (&v)[M], int seg, int K, int lin
     seg_last<C, M>(v, r, coef, X);
 }
 
+// ------------------------------------------- reverse-step sums (adjoint)
+//
+// The reverse step needs, per substrate and axis, sum y^T (L_N x) and
+// sum y^T x, where y is the transposed sweep's output and x the forward
+// sweep's output on the same lines, and (L_N x)_i = [i > 0](x_i - x_{i-1})
+// + [i < n-1](x_i - x_{i+1}) is the zero-flux Laplacian.  A transposed sweep
+// holds y in registers, so it forms the sums itself: each thread streams x
+// along its segment (with the one neighbour on each side), then the
+// segments of a line are added in order in LDS and the line's two sums are
+// written, one pair per line.  Padding slots have y = 0 and add nothing.
+
+// Sums of one segment: x_{i0 + k} at xp[k * st] for the real slots k <= last
+// (last >= 0); x_{i0 - 1} at xp[-st] when i0 > 0.  The loads run four at a
+// time behind a compiler barrier, so they do not all become live at once
+// beside the M values of y.
+template <typename C, int M, bool NT, typename T>
+__device__ __forceinline__ void seg_adjoint_sums(const C (&y)[M], const T* xp, int64_t st, int last, bool left,
+                                                 double& a0, double& a1)
+{
+    auto ld = [&](int64_t off) -> double {
+        if constexpr (NT) return (double)__builtin_nontemporal_load(&xp[off]);
+        else return (double)xp[off];
+    };
+    double xl = left ? ld(-st) : 0.0;
+    double xc = ld(0);
+    a0 = 0.0;
+    a1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        if ((k & 3) == 0) asm volatile("" ::: "memory");
+        const double xn = ld((int64_t)(k + 1 <= last ? k + 1 : last) * st);
+        double lx = 0.0;
+        if (k > 0 || left) lx += xc - xl;
+        if (k + 1 <= last) lx += xc - xn;
+        if (k <= last) {
+            a0 += (double)y[k] * lx;
+            a1 += (double)y[k] * xc;
+        }
+        xl = xc;
+        xc = xn;
+    }
+}
+
+// Adds the (a0, a1) of every (segment, line) slot of the block in segment
+// order and writes each valid line's pair to out[2 L], L = L0 + line.  The
+// carry arrays sc of solve_segment are reused (they hold at least 2 doubles
+// per slot in either layout), so this must follow the solve; every thread
+// of the block calls it.
+template <typename C>
+__device__ __forceinline__ void line_sums_store(double a0, double a1, int seg, int K, int line, int nl, C* sc,
+                                                bool par, bool writer, double* out, int64_t L0, int nvalid)
+{
+    const int KP = scan_kp(K, nl, (int)blockDim.x, par);
+    const int A = KP ? nl * (KP + 1) : K * nl;
+    double* s0 = reinterpret_cast<double*>(sc);
+    double* s1 = s0 + A;
+    __syncthreads();   // the solve's last reads of the carry arrays are done
+    if (writer) {
+        const int slot = KP ? line * (KP + 1) + seg : seg * nl + line;
+        s0[slot] = a0;
+        s1[slot] = a1;
+    }
+    __syncthreads();
+    const int l = (int)threadIdx.x;
+    if (l < nl && l < nvalid) {
+        double b0 = 0.0, b1 = 0.0;
+        for (int j = 0; j < K; ++j) {
+            const int sl = KP ? l * (KP + 1) + j : j * nl + l;
+            b0 += s0[sl];
+            b1 += s1[sl];
+        }
+        out[2 * (L0 + l) + 0] = b0;
+        out[2 * (L0 + l) + 1] = b1;
+    }
+}
+
 template <typename T> struct Vec16;
 template <> struct Vec16<double> { using type = double2; };
 template <> struct Vec16<float> { using type = float4; };

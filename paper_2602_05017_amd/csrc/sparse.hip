@@ -183,6 +183,54 @@ __global__ __launch_bounds__(256) void k_adj_final(const double* __restrict__ pa
     }
 }
 
+// Second stage of the per-line sums formed inside the transposed sweeps:
+// block (s, a) adds the pairs of the lines L = s, s + S, s + 2S, ... of axis
+// a, thread t taking every 256th of them in order, then a fixed-order tree:
+// deterministic.
+struct LineParts {
+    const double* p[3];
+    int64_t n[3];
+};
+
+__global__ __launch_bounds__(256) void k_adj_line_final(LineParts lp, int S, double* __restrict__ out)
+{
+    __shared__ double s0[256], s1[256];
+    const int s = blockIdx.x, a = blockIdx.y;
+    const double* part = lp.p[a];
+    const int64_t n = lp.n[a];
+    double a0 = 0.0, a1 = 0.0;
+    for (int64_t L = s + (int64_t)S * threadIdx.x; L < n; L += (int64_t)S * 256) {
+        a0 += part[2 * L + 0];
+        a1 += part[2 * L + 1];
+    }
+    s0[threadIdx.x] = a0;
+    s1[threadIdx.x] = a1;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s0[threadIdx.x] += s0[threadIdx.x + w];
+            s1[threadIdx.x] += s1[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[((int64_t)a * S + s) * 2 + 0] = s0[0];
+        out[((int64_t)a * S + s) * 2 + 1] = s1[0];
+    }
+}
+
+hipError_t launch_adjoint_line_final(double* const part[3], const int64_t nlines[3], int S, double* out,
+                                     hipStream_t st)
+{
+    LineParts lp;
+    for (int a = 0; a < 3; ++a) {
+        lp.p[a] = part[a];
+        lp.n[a] = nlines[a];
+    }
+    hipLaunchKernelGGL(k_adj_line_final, dim3((unsigned)S, 3), dim3(256), 0, st, lp, S, out);
+    return hipGetLastError();
+}
+
 int64_t adjoint_reduce_blocks(int64_t nvox)
 {
     int64_t b = (nvox + 255) / 256;

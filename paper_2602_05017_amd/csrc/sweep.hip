@@ -79,10 +79,13 @@ AxisGeom zslab_geom(int axis, int64_t nx, int64_t ny, int64_t nz, int32_t S, int
 
 // ------------------------------------------------------------ kind 0 (line)
 
-template <typename T, typename C, bool TR>
+// RED (transposed sweeps only): then sum y (L_N xf) and y xf along the
+// line, written to part[2 L] with L the thread's line index.
+template <typename T, typename C, bool TR, bool RED>
 __global__ __launch_bounds__(256) void k_sweep_line(const T* in, T* out, AxisGeom g,
                                                     const C* __restrict__ invd,
-                                                    const C* __restrict__ rr)
+                                                    const C* __restrict__ rr,
+                                                    const T* __restrict__ xf, double* __restrict__ part)
 {
     const int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (L >= g.inner * g.outer) return;
@@ -115,6 +118,20 @@ __global__ __launch_bounds__(256) void k_sweep_line(const T* in, T* out, AxisGeo
         for (int64_t i = n - 1; i >= 0; --i) {
             y = invd[i * S + s] * ((C)out[base + i * st] + r * y);
             out[base + i * st] = (T)y;
+        }
+        if constexpr (RED) {
+            double a0 = 0.0, a1 = 0.0;
+            for (int64_t i = 0; i < n; ++i) {
+                const double xc = (double)xf[base + i * st];
+                double lx = 0.0;
+                if (i > 0) lx += xc - (double)xf[base + (i - 1) * st];
+                if (i < n - 1) lx += xc - (double)xf[base + (i + 1) * st];
+                const double yi = (double)out[base + i * st];
+                a0 += yi * lx;
+                a1 += yi * xc;
+            }
+            part[2 * L + 0] = a0;
+            part[2 * L + 1] = a1;
         }
     }
 }
@@ -198,11 +215,15 @@ __device__ __forceinline__ void build_comp_rows(C* tab, const C* __restrict__ co
 // 1 its LDS copy in [s][segment][k] layout, 2 rows built in LDS from the
 // exact compressed table comp ([s][H + 2]: head, interior constant, last
 // slot), so that a segment inside the constant interior needs no table.
-template <typename T, typename C, int M, bool TR, int COEF, bool XROWS, int AX>
+// RED (transposed sweeps only): also form the reverse step's per-line sums
+// from y and the forward sweep's output xf (seg_adjoint_sums), written to
+// part[2 L], L = by * inner + p.
+template <typename T, typename C, int M, bool TR, int COEF, bool XROWS, int AX, bool RED>
 __global__ __launch_bounds__(1024) void k_sweep_seg_strided(const T* in, T* out, AxisGeom g,
                                                             const C* __restrict__ invd,
                                                             const C* __restrict__ rr, int lpw, int SP,
-                                                            FastDiv divS, const C* __restrict__ comp, int H)
+                                                            FastDiv divS, const C* __restrict__ comp, int H,
+                                                            const T* __restrict__ xf, double* __restrict__ part)
 {
     uint32_t bx, by;
     xcd_tile(bx, by);
@@ -279,6 +300,13 @@ __global__ __launch_bounds__(1024) void k_sweep_seg_strided(const T* in, T* out,
         for (int k = 0; k < M; ++k)
             if (k < cnt) op[k * st] = (T)v[k];
     }
+    if constexpr (RED) {
+        double a0 = 0.0, a1 = 0.0;
+        if (cnt > 0) seg_adjoint_sums<C, M, NT>(v, xf + base, st, (int)last, i0 > 0, a0, a1);
+        const int64_t p_first = (int64_t)bx * lpw;
+        line_sums_store<C>(a0, a1, seg, K, line, lpw, sc, false, true, part,
+                           (int64_t)by * g.inner + p_first, (int)min((int64_t)lpw, g.inner - p_first));
+    }
 }
 
 // ------------------------------------------------------- kind 2 (x, LDS tile)
@@ -291,30 +319,14 @@ __global__ __launch_bounds__(1024) void k_sweep_seg_strided(const T* in, T* out,
 // of line (r, s) from registers, writes it back, and the block stores the
 // rows with coalesced accesses.
 
-template <typename T, typename C, int M, bool TR>
-__global__ __launch_bounds__(512) void k_sweep_seg_xtile(const T* in, T* out, AxisGeom g,
-                                                         const C* __restrict__ invd,
-                                                         const C* __restrict__ rr, int R, int K,
-                                                         int SB, uint32_t tile_bytes,
-                                                         FastDiv divL, FastDiv divMS, bool vec)
+// Load `tot` elements of src (consecutive rows) into the padded LDS tile.
+// Loads are issued UNR at a time per thread so that many are in flight before
+// the first LDS write waits for its data; indices past the end are clamped so
+// every load stays in bounds.
+template <typename T, int M>
+__device__ __forceinline__ void xtile_load_rows(T* tile, const T* src, uint32_t tot, uint32_t L, uint32_t MS,
+                                                uint32_t RS, int SB, FastDiv divL, FastDiv divMS, bool vec)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    T* tile = reinterpret_cast<T*>(smem);
-    const int S = g.S;
-    const int nl = R * S;
-    C* sc = reinterpret_cast<C*>(smem + tile_bytes);
-    const uint32_t L = (uint32_t)(g.n * S);          // row length
-    const uint32_t MS = (uint32_t)(M * S);
-    const uint32_t RS = (uint32_t)(K * SB);           // tile row stride
-    const int64_t o0 = (int64_t)blockIdx.x * R;
-    const int nrows = (int)min((int64_t)R, g.outer - o0);
-    const uint32_t tot = (uint32_t)nrows * L;
-    const T* src = in + o0 * (int64_t)L;
-    T* dst = out + o0 * (int64_t)L;
-
-    // Loads are issued UNR at a time per thread so that many are in flight
-    // before the first LDS write waits for its data; indices past the end
-    // are clamped so every load stays in bounds.
     constexpr int UNR = 8;
     if (vec) {
         // 16-byte chunks: a chunk never straddles a segment block (M*S, SB and
@@ -362,6 +374,34 @@ __global__ __launch_bounds__(512) void k_sweep_seg_xtile(const T* in, T* out, Ax
             }
         }
     }
+}
+
+// RED (transposed sweeps only): after y has been stored, the forward sweep's
+// output xf of the same rows is staged through the tile as well, and the
+// reverse step's per-line sums are written to part[2 L], L = row * S + s.
+template <typename T, typename C, int M, bool TR, bool RED>
+__global__ __launch_bounds__(512) void k_sweep_seg_xtile(const T* in, T* out, AxisGeom g,
+                                                         const C* __restrict__ invd,
+                                                         const C* __restrict__ rr, int R, int K,
+                                                         int SB, uint32_t tile_bytes,
+                                                         FastDiv divL, FastDiv divMS, bool vec,
+                                                         const T* __restrict__ xf, double* __restrict__ part)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* tile = reinterpret_cast<T*>(smem);
+    const int S = g.S;
+    const int nl = R * S;
+    C* sc = reinterpret_cast<C*>(smem + tile_bytes);
+    const uint32_t L = (uint32_t)(g.n * S);          // row length
+    const uint32_t MS = (uint32_t)(M * S);
+    const uint32_t RS = (uint32_t)(K * SB);           // tile row stride
+    const int64_t o0 = (int64_t)blockIdx.x * R;
+    const int nrows = (int)min((int64_t)R, g.outer - o0);
+    const uint32_t tot = (uint32_t)nrows * L;
+    const T* src = in + o0 * (int64_t)L;
+    T* dst = out + o0 * (int64_t)L;
+
+    xtile_load_rows<T, M>(tile, src, tot, L, MS, RS, SB, divL, divMS, vec);
     __syncthreads();
 
     const int t = threadIdx.x;
@@ -417,6 +457,35 @@ __global__ __launch_bounds__(512) void k_sweep_seg_xtile(const T* in, T* out, Ax
             const uint32_t sg = divMS.div(q);
             dst[e] = tile[rw2 * RS + sg * SB + (q - sg * MS)];
         }
+    }
+    if constexpr (RED) {
+        __syncthreads();   // the stores above have read the tile
+        xtile_load_rows<T, M>(tile, xf + o0 * (int64_t)L, tot, L, MS, RS, SB, divL, divMS, vec);
+        __syncthreads();
+        double a0 = 0.0, a1 = 0.0;
+        if (cnt > 0) {
+            // the segment's x values in the tile; x_{i0-1} is slot M-1 of segment j-1
+            const T* xs = tile + rw * RS + j * SB + s;
+            const T* xl = xs - SB + (M - 1) * S;
+            double xm = i0 > 0 ? (double)*xl : 0.0;
+            double xc = (double)xs[0];
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                // x_{i0+k+1}: slot k+1 of this segment, or slot 0 of segment j+1
+                const T* nx = k + 1 < M ? xs + (k + 1) * S : xs + SB;
+                const double xn = k + 1 <= last ? (double)*nx : 0.0;
+                double lx = 0.0;
+                if (k > 0 || i0 > 0) lx += xc - xm;
+                if (k + 1 <= last) lx += xc - xn;
+                if (k <= last) {
+                    a0 += (double)v[k] * lx;
+                    a1 += (double)v[k] * xc;
+                }
+                xm = xc;
+                xc = xn;
+            }
+        }
+        line_sums_store<C>(a0, a1, j, K, active ? rw * S + s : 0, nl, sc, true, active, part, o0 * S, nrows * S);
     }
 }
 
@@ -854,9 +923,10 @@ static hipError_t launch_xpipe(const SweepPlan& p, const AxisGeom& g, const T* i
     return hipErrorInvalidValue;
 }
 
-template <typename T, typename C, bool TR, int M>
+template <typename T, typename C, bool TR, int M, bool RED>
 static hipError_t launch_seg(const SweepPlan& p, const AxisGeom& g, const T* in, T* out,
-                             const C* invd, const C* r, const C* comp, int compH, hipStream_t st)
+                             const C* invd, const C* r, const C* comp, int compH, hipStream_t st,
+                             const T* xf, double* part)
 {
     if (p.kind == PLAN_SEG_STRIDED || p.kind == PLAN_SEG_XROWS) {
         const bool xrows = p.kind == PLAN_SEG_XROWS;
@@ -894,29 +964,29 @@ static hipError_t launch_seg(const SweepPlan& p, const AxisGeom& g, const T* in,
         const bool zaxis = g.axis == 2;
         const FastDiv dS((uint32_t)g.S);
         if (xrows && use_comp)
-            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 2, true, 0>), grid, dim3(threads), scan + ctab, st,
-                               in, out, gg, invd, r, p.lpw, SP, dS, comp, compH);
+            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 2, true, 0, RED>), grid, dim3(threads), scan + ctab,
+                               st, in, out, gg, invd, r, p.lpw, SP, dS, comp, compH, xf, part);
         else if (xrows && lds_tab)
-            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 1, true, 0>), grid, dim3(threads), scan + tab, st,
-                               in, out, gg, invd, r, p.lpw, SP, dS, comp, compH);
+            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 1, true, 0, RED>), grid, dim3(threads), scan + tab,
+                               st, in, out, gg, invd, r, p.lpw, SP, dS, comp, compH, xf, part);
         else if (xrows)
-            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 0, true, 0>), grid, dim3(threads), scan, st, in,
-                               out, gg, invd, r, p.lpw, SP, dS, comp, compH);
+            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 0, true, 0, RED>), grid, dim3(threads), scan, st,
+                               in, out, gg, invd, r, p.lpw, SP, dS, comp, compH, xf, part);
         else if (use_comp && zaxis)
-            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 2, false, 2>), grid, dim3(threads), scan + ctab,
-                               st, in, out, gg, invd, r, p.lpw, SP, dS, comp, compH);
+            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 2, false, 2, RED>), grid, dim3(threads),
+                               scan + ctab, st, in, out, gg, invd, r, p.lpw, SP, dS, comp, compH, xf, part);
         else if (use_comp)
-            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 2, false, 1>), grid, dim3(threads), scan + ctab,
-                               st, in, out, gg, invd, r, p.lpw, SP, dS, comp, compH);
+            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 2, false, 1, RED>), grid, dim3(threads),
+                               scan + ctab, st, in, out, gg, invd, r, p.lpw, SP, dS, comp, compH, xf, part);
         else if (lds_tab && zaxis)
-            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 1, false, 2>), grid, dim3(threads), scan + tab, st,
-                               in, out, gg, invd, r, p.lpw, SP, dS, comp, compH);
+            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 1, false, 2, RED>), grid, dim3(threads),
+                               scan + tab, st, in, out, gg, invd, r, p.lpw, SP, dS, comp, compH, xf, part);
         else if (lds_tab)
-            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 1, false, 1>), grid, dim3(threads), scan + tab, st,
-                               in, out, gg, invd, r, p.lpw, SP, dS, comp, compH);
+            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 1, false, 1, RED>), grid, dim3(threads),
+                               scan + tab, st, in, out, gg, invd, r, p.lpw, SP, dS, comp, compH, xf, part);
         else
-            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 0, false, 1>), grid, dim3(threads), scan, st, in,
-                               out, gg, invd, r, p.lpw, SP, dS, comp, compH);
+            hipLaunchKernelGGL((k_sweep_seg_strided<T, C, M, TR, 0, false, 1, RED>), grid, dim3(threads), scan, st,
+                               in, out, gg, invd, r, p.lpw, SP, dS, comp, compH, xf, part);
     } else {
         const int K = (int)ceil_div(g.n, M);
         const int SB = xtile_sb(M, g.S, (int)sizeof(T));
@@ -926,56 +996,65 @@ static hipError_t launch_seg(const SweepPlan& p, const AxisGeom& g, const T* in,
         const int64_t VW = 16 / sizeof(T);
         const bool vec = (M * g.S) % VW == 0 && SB % VW == 0 && (g.n * g.S) % VW == 0 &&
                          (reinterpret_cast<uintptr_t>(in) % 16) == 0 && (reinterpret_cast<uintptr_t>(out) % 16) == 0;
-        // kind 4 needs 16-byte aligned fields; otherwise its plan runs as kind 2
-        if (p.kind == PLAN_SEG_XPIPE && vec) return launch_xpipe<T, C, TR, M>(p, g, in, out, invd, r, st);
-        hipLaunchKernelGGL((k_sweep_seg_xtile<T, C, M, TR>), grid, dim3(p.w * 64), lds, st, in, out,
+        // kind 4 needs 16-byte aligned fields; otherwise (and for the reverse
+        // step's fused sums) its plan runs as kind 2
+        if (!RED && p.kind == PLAN_SEG_XPIPE && vec) return launch_xpipe<T, C, TR, M>(p, g, in, out, invd, r, st);
+        const bool vx = vec && (!RED || (reinterpret_cast<uintptr_t>(xf) % 16) == 0);
+        hipLaunchKernelGGL((k_sweep_seg_xtile<T, C, M, TR, RED>), grid, dim3(p.w * 64), lds, st, in, out,
                            g, invd, r, p.lpw, K, SB, tile_bytes, FastDiv((uint32_t)(g.n * g.S)),
-                           FastDiv((uint32_t)(M * g.S)), vec);
+                           FastDiv((uint32_t)(M * g.S)), vx, xf, part);
     }
     return hipGetLastError();
 }
 
-template <typename T, typename C, bool TR>
+template <typename T, typename C, bool TR, bool RED>
 static hipError_t launch_typed(const SweepPlan& p, const AxisGeom& g, const void* in, void* out,
-                               const void* invd, const void* r, const void* comp, int compH, hipStream_t st)
+                               const void* invd, const void* r, const void* comp, int compH, hipStream_t st,
+                               const AdjSums& red)
 {
     const T* i = static_cast<const T*>(in);
     T* o = static_cast<T*>(out);
     const C* cf = static_cast<const C*>(invd);
     const C* rr = static_cast<const C*>(r);
     const C* cc = static_cast<const C*>(comp);
+    const T* xf = static_cast<const T*>(red.x);
     if (p.kind == PLAN_LINE) {
         const int64_t lines = g.inner * g.outer;
-        hipLaunchKernelGGL((k_sweep_line<T, C, TR>), dim3((unsigned)ceil_div(lines, 256)), dim3(256), 0,
-                           st, i, o, g, cf, rr);
+        hipLaunchKernelGGL((k_sweep_line<T, C, TR, RED>), dim3((unsigned)ceil_div(lines, 256)), dim3(256), 0,
+                           st, i, o, g, cf, rr, xf, red.part);
         return hipGetLastError();
     }
     switch (p.m) {
-        case 4: return launch_seg<T, C, TR, 4>(p, g, i, o, cf, rr, cc, compH, st);
-        case 8: return launch_seg<T, C, TR, 8>(p, g, i, o, cf, rr, cc, compH, st);
-        case 16: return launch_seg<T, C, TR, 16>(p, g, i, o, cf, rr, cc, compH, st);
-        case 32: return launch_seg<T, C, TR, 32>(p, g, i, o, cf, rr, cc, compH, st);
+        case 4: return launch_seg<T, C, TR, 4, RED>(p, g, i, o, cf, rr, cc, compH, st, xf, red.part);
+        case 8: return launch_seg<T, C, TR, 8, RED>(p, g, i, o, cf, rr, cc, compH, st, xf, red.part);
+        case 16: return launch_seg<T, C, TR, 16, RED>(p, g, i, o, cf, rr, cc, compH, st, xf, red.part);
+        case 32: return launch_seg<T, C, TR, 32, RED>(p, g, i, o, cf, rr, cc, compH, st, xf, red.part);
         default: return hipErrorInvalidValue;
     }
 }
 
+template <typename T, typename C>
+static hipError_t launch_dir(bool transposed, const SweepPlan& plan, const AxisGeom& g, const void* in, void* out,
+                             const void* invd, const void* r, const void* comp, int compH, hipStream_t st,
+                             const AdjSums& red)
+{
+    if (!transposed) return launch_typed<T, C, false, false>(plan, g, in, out, invd, r, comp, compH, st, red);
+    if (red.part) return launch_typed<T, C, true, true>(plan, g, in, out, invd, r, comp, compH, st, red);
+    return launch_typed<T, C, true, false>(plan, g, in, out, invd, r, comp, compH, st, red);
+}
+
 hipError_t launch_sweep(int dtype, bool transposed, const SweepPlan& plan, const AxisGeom& g,
                         const void* in, void* out, const void* invd, const void* r, const void* comp, int compH,
-                        hipStream_t st)
+                        hipStream_t st, const AdjSums& red)
 {
     if (g.inner * g.outer == 0) return hipSuccess;
+    if (red.part && (!transposed || !red.x || g.p0 != 0 || g.o0 != 0)) return hipErrorInvalidValue;
     switch (dtype) {
-        case DT_F64:
-            return transposed ? launch_typed<double, double, true>(plan, g, in, out, invd, r, comp, compH, st)
-                              : launch_typed<double, double, false>(plan, g, in, out, invd, r, comp, compH, st);
-        case DT_F32:
-            return transposed ? launch_typed<float, double, true>(plan, g, in, out, invd, r, comp, compH, st)
-                              : launch_typed<float, double, false>(plan, g, in, out, invd, r, comp, compH, st);
+        case DT_F64: return launch_dir<double, double>(transposed, plan, g, in, out, invd, r, comp, compH, st, red);
+        case DT_F32: return launch_dir<float, double>(transposed, plan, g, in, out, invd, r, comp, compH, st, red);
         case DT_F32_FAST:
-            return transposed ? launch_typed<float, float, true>(plan, g, in, out, invd, r, comp, compH, st)
-                              : launch_typed<float, float, false>(plan, g, in, out, invd, r, comp, compH, st);
-        default:
-            return hipErrorInvalidValue;
+            return launch_dir<float, float>(transposed, plan, g, in, out, invd, r, comp, compH, st, red);
+        default: return hipErrorInvalidValue;
     }
 }
 
