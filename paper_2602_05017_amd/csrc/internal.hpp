@@ -100,16 +100,6 @@ hipError_t launch_dirichlet(int dtype, void* u, const int64_t* elem, const doubl
                             int64_t cnt, hipStream_t stream);
 hipError_t launch_mask(int dtype, void* g, const int64_t* elem, int64_t cnt, hipStream_t stream);
 
-// Adjoint reduction, first stage: partials[(s*nblocks + b)*2 + {0,1}] =
-// block b's sums of y*(L_N x) and y*x over the elements of substrate s
-// (fixed order); nblocks = adjoint_reduce_blocks(nvox) <= max_blocks.
-hipError_t launch_adjoint_partials(int dtype, const void* y, const void* x, const AxisGeom& g, int64_t nelem,
-                                   double* partials, int64_t max_blocks, hipStream_t stream);
-// Second stage for naxes slots of 2*S*nblocks partials each:
-// out[(a*S + s)*2 + {0,1}] = sum over b in order.
-hipError_t launch_adjoint_final(const double* partials, int64_t nblocks, int S, int naxes, double* out,
-                                hipStream_t stream);
-int64_t adjoint_reduce_blocks(int64_t nvox);
 // Second stage of the per-line sums: out[(a*S + s)*2 + {0,1}] = the sum over
 // the lines L = s (mod S) of axis a (part[a], nlines[a] lines), in line order.
 hipError_t launch_adjoint_line_final(double* const part[3], const int64_t nlines[3], int S, double* out,

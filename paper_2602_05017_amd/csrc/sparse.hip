@@ -5,8 +5,9 @@
 //               on the host (production and uptake by cells, Sec. 5.3)
 //   dirichlet   u[e] <- value at active Dirichlet entries (Sec. 2, 7 stages)
 //   adjoint     transposes: mask (zero at Dirichlet entries), source
-//               (multiply by invQ), and the per-substrate sums
-//               sum y*(L_N x) and sum y*x behind dL/dD and dL/dlambda
+//               (multiply by invQ), and the second stage of the
+//               per-substrate sums sum y*(L_N x) and sum y*x behind dL/dD
+//               and dL/dlambda (the transposed sweeps form the per-line sums)
 #include "internal.hpp"
 
 namespace bfvm {
@@ -96,92 +97,6 @@ hipError_t launch_mask(int dtype, void* g, const int64_t* elem, int64_t cnt, hip
 }
 
 // ------------------------------------------------------ adjoint reductions
-//
-// Grid (nblocks, S).  Block b of substrate s visits voxels v = b*256 + t,
-// stepping by nblocks*256, element e = v*S + s.  Along the sweep axis the
-// element's position is i = (v / vstride) % n, where vstride is the voxel
-// stride of the axis, and (L_N x)_i = [i>0](x_i - x_{i-1}) + [i<n-1](x_i - x_{i+1}).
-// Per-thread sums are combined by a fixed-shape LDS tree, then the partials
-// of all blocks are added in block order, so the result does not depend on
-// scheduling.
-
-// floor(v / d) for 0 <= v < 2^51 through the FP64 reciprocal: (v + 1/2) / d
-// lies at least 1/(2d) from an integer and the two roundings err by less
-// than (v + 1/2) 2^-52 / d, so truncation gives the exact quotient.
-__device__ __forceinline__ int64_t div_fp(int64_t v, double inv_d)
-{
-    return (int64_t)(((double)v + 0.5) * inv_d);
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_adj_partials(const T* __restrict__ y, const T* __restrict__ x,
-                                                      int64_t nvox, int64_t vstride, int64_t n, int S,
-                                                      double inv_vstride, double inv_n,
-                                                      double* __restrict__ partials)
-{
-    __shared__ double s0[256], s1[256];
-    const int s = blockIdx.y;
-    const int64_t nb = gridDim.x;
-    const int64_t est = vstride * S;   // element stride along the axis
-    double a0 = 0.0, a1 = 0.0;
-    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < nvox; v += nb * 256) {
-        const int64_t q = div_fp(v, inv_vstride);
-        const int64_t i = q - div_fp(q, inv_n) * n;
-        const int64_t e = v * S + s;
-        const double xe = (double)x[e];
-        double lx = 0.0;
-        if (i > 0) lx += xe - (double)x[e - est];
-        if (i < n - 1) lx += xe - (double)x[e + est];
-        const double ye = (double)y[e];
-        a0 += ye * lx;
-        a1 += ye * xe;
-    }
-    s0[threadIdx.x] = a0;
-    s1[threadIdx.x] = a1;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            s0[threadIdx.x] += s0[threadIdx.x + w];
-            s1[threadIdx.x] += s1[threadIdx.x + w];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        partials[((int64_t)s * nb + blockIdx.x) * 2 + 0] = s0[0];
-        partials[((int64_t)s * nb + blockIdx.x) * 2 + 1] = s1[0];
-    }
-}
-
-// Second stage, for all axes at once: block (s, a) sums the nb partial pairs
-// of substrate s in axis a's slot (partials + a * 2 S nb), each thread a
-// fixed strided subset, then a fixed-order tree: deterministic.  out[a][s][2].
-__global__ __launch_bounds__(256) void k_adj_final(const double* __restrict__ partials_all, int64_t nb, int S,
-                                                   double* __restrict__ out_all)
-{
-    __shared__ double s0[256], s1[256];
-    const int s = blockIdx.x;
-    const double* partials = partials_all + (int64_t)blockIdx.y * 2 * S * nb;
-    double* out = out_all + (int64_t)blockIdx.y * 2 * S;
-    double a0 = 0.0, a1 = 0.0;
-    for (int64_t b = threadIdx.x; b < nb; b += 256) {
-        a0 += partials[((int64_t)s * nb + b) * 2 + 0];
-        a1 += partials[((int64_t)s * nb + b) * 2 + 1];
-    }
-    s0[threadIdx.x] = a0;
-    s1[threadIdx.x] = a1;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            s0[threadIdx.x] += s0[threadIdx.x + w];
-            s1[threadIdx.x] += s1[threadIdx.x + w];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        out[s * 2 + 0] = s0[0];
-        out[s * 2 + 1] = s1[0];
-    }
-}
 
 // Second stage of the per-line sums formed inside the transposed sweeps:
 // block (s, a) adds the pairs of the lines L = s, s + S, s + 2S, ... of axis
@@ -228,32 +143,6 @@ hipError_t launch_adjoint_line_final(double* const part[3], const int64_t nlines
         lp.n[a] = nlines[a];
     }
     hipLaunchKernelGGL(k_adj_line_final, dim3((unsigned)S, 3), dim3(256), 0, st, lp, S, out);
-    return hipGetLastError();
-}
-
-int64_t adjoint_reduce_blocks(int64_t nvox)
-{
-    int64_t b = (nvox + 255) / 256;
-    return b < 1024 ? (b < 1 ? 1 : b) : 1024;
-}
-
-hipError_t launch_adjoint_partials(int dtype, const void* y, const void* x, const AxisGeom& g, int64_t nelem,
-                                   double* partials, int64_t max_blocks, hipStream_t st)
-{
-    const int S = g.S;
-    const int64_t nvox = nelem / S;
-    const int64_t nb = adjoint_reduce_blocks(nvox);
-    if (nb > max_blocks || nvox >= ((int64_t)1 << 51)) return hipErrorInvalidValue;
-    const int64_t vstride = g.stride / S;
-    DISPATCH_T(dtype, hipLaunchKernelGGL(k_adj_partials<T>, dim3((unsigned)nb, (unsigned)S), dim3(256), 0,
-                                         st, static_cast<const T*>(y), static_cast<const T*>(x), nvox,
-                                         vstride, g.n, S, 1.0 / (double)vstride, 1.0 / (double)g.n, partials));
-    return hipGetLastError();
-}
-
-hipError_t launch_adjoint_final(const double* partials, int64_t nb, int S, int naxes, double* out, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_adj_final, dim3((unsigned)S, (unsigned)naxes), dim3(256), 0, st, partials, nb, S, out);
     return hipGetLastError();
 }
 
