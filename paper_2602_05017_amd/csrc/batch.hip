@@ -125,6 +125,8 @@ __device__ __forceinline__ SweepShape sweep_shape(const BDomain& d, int axis)
 // Element indices are signed 32-bit (a batched domain has < 2^31 elements):
 // a padding slot's index base + last * st, with last < 0, is then the line's
 // last element, computed without leaving the domain.
+__device__ __forceinline__ int lpw_log2(int lpw) { return 31 - __clz(lpw); }
+
 struct TileSpot {
     int base;        // element index of the thread's first slot
     int last;        // n - 1 - i0: slots k > last are padding
@@ -132,22 +134,24 @@ struct TileSpot {
     int s;           // substrate
 };
 
-__device__ __forceinline__ TileSpot tile_spot(const SweepShape& q, int S, int lpw, int M, int64_t ox, int64_t oy)
+__device__ __forceinline__ TileSpot tile_spot(const SweepShape& q, int S, const FastDiv& dS, int lpw, int M,
+                                              uint32_t ox, uint32_t oy)
 {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int line = lane % lpw;
-    const int seg = wave * (64 / lpw) + lane / lpw;
+    const int line = lane & (lpw - 1);   // lpw is 16, 32 or 64
+    const int seg = wave * (64 >> lpw_log2(lpw)) + (lane >> lpw_log2(lpw));
     const uint32_t inner = (uint32_t)q.inner;
     const uint32_t p = (uint32_t)ox * lpw + line;
     const bool valid = p < inner;
     const uint32_t pa = valid ? p : inner - 1;
     TileSpot t;
-    t.s = (int)(pa % (uint32_t)S);
+    const uint32_t row = dS.div(pa);   // pa * S < 2^39: exact
+    t.s = (int)(pa - row * (uint32_t)S);
     const int i0 = seg * M;
     t.last = (int)q.n - 1 - i0;
     t.cnt = !valid || t.last < 0 ? 0 : (t.last >= M ? M : t.last + 1);
-    const int line0 = q.xrows ? (int)((pa / S) * (uint32_t)q.row_len) + t.s
+    const int line0 = q.xrows ? (int)(row * (uint32_t)q.row_len) + t.s
                               : (int)oy * (int)q.outer_stride + (int)pa;
     t.base = line0 + i0 * (int)q.stride;
     return t;
@@ -168,8 +172,8 @@ __device__ __forceinline__ void tile_solve_store(T* out, const TileSpot& t, int 
     const int K = blockDim.x / lpw;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int line = lane % lpw;
-    const int seg = wave * (64 / lpw) + lane / lpw;
+    const int line = lane & (lpw - 1);   // lpw is 16, 32 or 64
+    const int seg = wave * (64 >> lpw_log2(lpw)) + (lane >> lpw_log2(lpw));
     const int i0 = seg * M;
 #pragma unroll
     for (int k = 0; k < M; ++k) v[k] = (C)raw[k];
@@ -192,14 +196,15 @@ __device__ __forceinline__ void tile_solve_store(T* out, const TileSpot& t, int 
 // added into acc[2 s], acc[2 s + 1] by substrate in line order.  Every
 // thread of the block calls this; lsum holds 2 doubles per line of the tile.
 template <typename T, typename C, int M>
-__device__ __forceinline__ void tile_sums(const C (&v)[M], const TileSpot& t, const SweepShape& q, int S, int lpw,
-                                          int64_t ox, const T* __restrict__ xf, C* sc, double* lsum, double* acc)
+__device__ __forceinline__ void tile_sums(const C (&v)[M], const TileSpot& t, const SweepShape& q, int S,
+                                          const FastDiv& dS, int lpw, uint32_t ox, const T* __restrict__ xf, C* sc,
+                                          double* lsum, double* acc)
 {
     const int K = blockDim.x / lpw;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int line = lane % lpw;
-    const int seg = wave * (64 / lpw) + lane / lpw;
+    const int line = lane & (lpw - 1);   // lpw is 16, 32 or 64
+    const int seg = wave * (64 >> lpw_log2(lpw)) + (lane >> lpw_log2(lpw));
     double a0 = 0.0, a1 = 0.0;
     if (t.cnt > 0) seg_adjoint_sums<C, M, false>(v, xf + t.base, (int64_t)q.stride, t.last, seg > 0, a0, a1);
     const int KP = scan_kp(K, lpw, (int)blockDim.x, true);
@@ -211,8 +216,8 @@ __device__ __forceinline__ void tile_sums(const C (&v)[M], const TileSpot& t, co
     s0[slot] = a0;
     s1[slot] = a1;
     __syncthreads();
-    const int64_t p0 = ox * lpw;
-    const int nvalid = (int)min((int64_t)lpw, q.inner - p0);
+    const uint32_t p0 = ox * (uint32_t)lpw;
+    const int nvalid = (int)min((int64_t)lpw, q.inner - (int64_t)p0);
     const int l = (int)threadIdx.x;
     if (l < nvalid) {
         double b0 = 0.0, b1 = 0.0;
@@ -226,7 +231,7 @@ __device__ __forceinline__ void tile_sums(const C (&v)[M], const TileSpot& t, co
     }
     __syncthreads();
     // line p0 + l belongs to substrate (p0 + l) % S
-    const int ph = (int)(p0 % S);
+    const int ph = (int)(p0 - dS.div(p0) * (uint32_t)S);
     for (int sub = (int)threadIdx.x; sub < S; sub += (int)blockDim.x) {
         double b0 = acc[2 * sub + 0], b1 = acc[2 * sub + 1];
         for (int l2 = (sub - ph + S) % S; l2 < nvalid; l2 += S) {
@@ -240,16 +245,17 @@ __device__ __forceinline__ void tile_sums(const C (&v)[M], const TileSpot& t, co
 
 // One tile; for transposed tiles also the parameter sums (xf, lsum, acc).
 template <typename T, typename C, int M, bool TR>
-__device__ __forceinline__ void batch_tile(const T* in, T* out, const SweepShape& q, int S, int lpw, int64_t ox,
-                                           int64_t oy, const C* __restrict__ invd, const C* __restrict__ rr, C* sc,
-                                           const T* __restrict__ xf, double* lsum, double* acc)
+__device__ __forceinline__ void batch_tile(const T* in, T* out, const SweepShape& q, int S, const FastDiv& dS,
+                                           int lpw, uint32_t ox, uint32_t oy, const C* __restrict__ invd,
+                                           const C* __restrict__ rr, C* sc, const T* __restrict__ xf, double* lsum,
+                                           double* acc)
 {
-    const TileSpot t = tile_spot(q, S, lpw, M, ox, oy);
+    const TileSpot t = tile_spot(q, S, dS, lpw, M, ox, oy);
     T raw[M];
     tile_load<T, M>(in, t, (int)q.stride, raw);
     C v[M];
     tile_solve_store<T, C, M, TR>(out, t, (int)q.stride, raw, S, lpw, invd, rr, sc, v);
-    if constexpr (TR) tile_sums<T, C, M>(v, t, q, S, lpw, ox, xf, sc, lsum, acc);
+    if constexpr (TR) tile_sums<T, C, M>(v, t, q, S, dS, lpw, ox, xf, sc, lsum, acc);
 }
 
 // acc: 2 * S doubles of the item's parameter sums (transposed items)
@@ -267,12 +273,18 @@ __device__ void batch_sweep_item(const BDomain& d, const BItem& it, C* sc, doubl
     const C* rr = static_cast<const C*>(d.r[it.axis]);
     if (TR)
         for (int sub = threadIdx.x; sub < d.S; sub += blockDim.x) acc[2 * sub] = acc[2 * sub + 1] = 0.0;
+    const FastDiv dS((uint32_t)d.S);
+    // tile t = oy * tpo + ox, stepped without a division per tile
+    uint32_t oy = (uint32_t)(it.a0 / tpo), ox = (uint32_t)(it.a0 - (int64_t)oy * tpo);
     for (int64_t t = it.a0; t < it.a1; ++t) {
-        const int64_t oy = t / tpo, ox = t - oy * tpo;
         if (it.m == 4)
-            batch_tile<T, C, 4, TR>(in, out, q, d.S, lpw, ox, oy, invd, rr, sc, xf, lsum, acc);
+            batch_tile<T, C, 4, TR>(in, out, q, d.S, dS, lpw, ox, oy, invd, rr, sc, xf, lsum, acc);
         else
-            batch_tile<T, C, 8, TR>(in, out, q, d.S, lpw, ox, oy, invd, rr, sc, xf, lsum, acc);
+            batch_tile<T, C, 8, TR>(in, out, q, d.S, dS, lpw, ox, oy, invd, rr, sc, xf, lsum, acc);
+        if (++ox == (uint32_t)tpo) {
+            ox = 0;
+            ++oy;
+        }
     }
     if (TR)
         for (int sub = threadIdx.x; sub < d.S; sub += blockDim.x) {
@@ -366,9 +378,15 @@ __global__ __launch_bounds__(kBatchThreads, (TR && M > 8) ? 2 : 4) void k_group_
     if (TR)
         for (int sub = threadIdx.x; sub < d.S; sub += blockDim.x) acc[2 * sub] = acc[2 * sub + 1] = 0.0;
     __syncthreads();
+    const FastDiv dS((uint32_t)d.S);
+    // tile t = oy * tpo + ox, stepped without a division per tile
+    uint32_t oy = (uint32_t)(it.a0 / tpo), ox = (uint32_t)(it.a0 - (int64_t)oy * tpo);
     for (int64_t t = it.a0; t < it.a1; ++t) {
-        const int64_t oy = t / tpo, ox = t - oy * tpo;
-        batch_tile<T, C, M, TR>(in, out, q, d.S, lpw, ox, oy, tab, rr, sc, xf, lsum, acc);
+        batch_tile<T, C, M, TR>(in, out, q, d.S, dS, lpw, ox, oy, tab, rr, sc, xf, lsum, acc);
+        if (++ox == (uint32_t)tpo) {
+            ox = 0;
+            ++oy;
+        }
     }
     if (TR)
         for (int sub = threadIdx.x; sub < d.S; sub += blockDim.x) {

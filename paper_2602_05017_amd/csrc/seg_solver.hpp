@@ -306,7 +306,7 @@ __device__ __forceinline__ void solve_segment(C (&v)[M], int seg, int K, int lin
 // written, one pair per line.  Padding slots have y = 0 and add nothing.
 
 // Sums of one segment: x_{i0 + k} at xp[k * st] for the real slots k <= last
-// (last >= 0); x_{i0 - 1} at xp[-st] when i0 > 0.  The loads run four at a
+// (last >= 0); x_{i0 - 1} at xp[-st] when i0 > 0.  The loads run eight at a
 // time behind a compiler barrier, so they do not all become live at once
 // beside the M values of y.
 template <typename C, int M, bool NT, typename T>
@@ -323,7 +323,7 @@ __device__ __forceinline__ void seg_adjoint_sums(const C (&y)[M], const T* xp, i
     a1 = 0.0;
 #pragma unroll
     for (int k = 0; k < M; ++k) {
-        if ((k & 3) == 0) asm volatile("" ::: "memory");
+        if ((k & 7) == 0) asm volatile("" ::: "memory");
         const double xn = ld((int64_t)(k + 1 <= last ? k + 1 : last) * st);
         double lx = 0.0;
         if (k > 0 || left) lx += xc - xl;
