@@ -309,9 +309,16 @@ int bfvm_field_free(void* field);
  * bfvm_batch_step / step_adjoint captures its graph again.  A setter must
  * not run while batch work is in flight (the batch calls below return only
  * after their work has finished).
- * Line lengths up to 256 are supported, with line length x substrates at
- * most 2048 on every axis (e.g. 256 voxels x 8 substrates).  The batch's calls are not
- * thread-safe; calls on one batch from several threads must be serialised.
+ * The grouped kernels take lines of up to 256 voxels, with line length x
+ * substrates at most 2048 on every axis (e.g. 256 voxels x 8 substrates),
+ * at most 256 substrates and fewer than 2^31 elements.  A member beyond
+ * these limits joins the same graph through its own grid's kernels (as
+ * bfvm_step with the plain schedule and the grid's plans; its reverse step
+ * as bfvm_step_adjoint, in the grid's own workspace), on a stream of its
+ * own beside the grouped launches; such a grid may hold one member only.
+ * The batch's calls are not thread-safe; calls on one batch from several
+ * threads must be serialised, and a member grid beyond the limits must not
+ * run its own reverse step while the batch's is in flight.
  */
 typedef struct bfvm_batch_s* bfvm_batch;
 
@@ -321,8 +328,8 @@ typedef struct bfvm_batch_s* bfvm_batch;
 /* grids[ndomains] (each with set_params done) and fields[ndomains] (device
  * pointers, each holding its grid's field).  stream = hipStream_t; NULL makes
  * the batch create its own non-blocking stream (graphs cannot capture the
- * null stream).  Errors: EINVAL (sizes, NULLs, line longer than 256 or
- * line x substrates above 2048), ESTATE (a grid without params), ENOMEM,
+ * null stream).  Errors: EINVAL (sizes, NULLs, a grid beyond the grouped
+ * limits given for two members), ESTATE (a grid without params), ENOMEM,
  * EDEVICE. */
 int bfvm_batch_create(bfvm_batch* out, int32_t ndomains, const bfvm_grid* grids, void* const* fields,
                       void* stream);
@@ -333,9 +340,11 @@ int bfvm_batch_destroy(bfvm_batch b);
  * mode resets the tile plans to the defaults.  Errors: EINVAL, EOFF. */
 int bfvm_batch_set_mode(bfvm_batch b, int32_t mode);
 
-/* Re-point the per-domain buffers (which = 0: fields, 1: gradients) without
- * re-capturing: the kernels read the pointers from device descriptors at
- * run time. */
+/* Re-point the per-domain buffers (which = 0: fields, 1: gradients).  The
+ * grouped kernels read the pointers from device descriptors at run time, so
+ * the graphs stay; a member beyond the grouped limits carries its pointers
+ * in its launches, and a change of one makes the next step or reverse step
+ * capture its graph again. */
 int bfvm_batch_set_fields(bfvm_batch b, int32_t which, void* const* ptrs);
 
 /* nsteps steps of every domain by replaying the captured graph, then waits
@@ -353,7 +362,8 @@ int bfvm_batch_step_eager(bfvm_batch b, int64_t nsteps);
  * changes).  grad_D, grad_lambda: HOST arrays of sum_{i} nsub(subset[i])
  * values, in subset order, INCREMENTED (per-item partial sums added on the
  * host in a fixed order: deterministic).  Allocates the subset's workspace
- * (three fields per domain) when the subset changes.
+ * (three fields per domain) when the subset changes; a member beyond the
+ * grouped limits uses (and on first use allocates) its grid's own.
  * Errors: EINVAL (incl. a repeated domain), ERANGE, ESTATE (no gradient
  * buffers), ENOMEM, EDEVICE. */
 int bfvm_batch_step_adjoint(bfvm_batch b, int32_t count, const int32_t* subset, double* grad_D,
@@ -367,7 +377,9 @@ int bfvm_batch_step_adjoint(bfvm_batch b, int32_t count, const int32_t* subset, 
  * change). */
 int bfvm_batch_autotune(bfvm_batch b, const char* cache_path, double* best_ms);
 
-/* Elements per thread (m) and lines per tile (lpw) of a domain's axis. */
+/* Elements per thread (m) and lines per tile (lpw) of a domain's axis.
+ * ESTATE for a member beyond the grouped limits (its grid's own plan,
+ * bfvm_get_plan, applies). */
 int bfvm_batch_get_plan(bfvm_batch b, int32_t domain, int32_t axis, int32_t* m, int32_t* lpw);
 
 /* Set a domain axis's plan by hand (the autotuner's choice otherwise):
@@ -377,7 +389,8 @@ int bfvm_batch_get_plan(bfvm_batch b, int32_t domain, int32_t axis, int32_t* m, 
  * transposed sweeps of an M = 16 axis run as M = 8 with half the lines per
  * tile (at least 16) where those still cover the line.  Errors: EINVAL
  * (NULL batch, unsupported or too small plan), ERANGE (domain or axis),
- * EDEVICE. */
+ * ESTATE (a member beyond the grouped limits: use bfvm_set_plan on its
+ * grid), EDEVICE. */
 int bfvm_batch_set_plan(bfvm_batch b, int32_t domain, int32_t axis, int32_t m, int32_t lpw);
 /* Work items of one forward step, kernel launches per step, work per item. */
 int bfvm_batch_info(bfvm_batch b, int64_t* items, int32_t* launches, int64_t* chunk_elems);

@@ -18,6 +18,12 @@
 // launches of each storage type form an independent chain on a stream of its
 // own, so the chains of FP64 and FP32 domains overlap on the device.
 //
+// Domains the grouped kernels cannot take (lines over 256 voxels, more than
+// 2048 coefficient-table entries on an axis, more than 256 substrates or
+// 2^31 elements) join the same graph through their own grid's kernels (the
+// single-grid sweeps, plain schedule, the grid's plans and, for the reverse
+// step, the grid's workspace), on one more chain of their own.
+//
 // Persistent mode (switched off): ONE launch per step whose blocks take the
 // items of all stages from an atomic queue and wait, through per-(domain,
 // stage) completion counters, for the previous stage of their own domain.
@@ -463,6 +469,10 @@ struct Program : ProgramLayout {
     BItem* d_items = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // members outside the grouped kernels' limits, run with their own grid's
+    // launches: one step (forward program) or one reverse step (adjoint)
+    std::vector<int32_t> big;
+    bool reverse = false;
 };
 
 void drop_graph(Program& P)
@@ -480,6 +490,21 @@ void free_program(Program& P)
     P.d_items = nullptr;
     P.items.clear();
     P.launches.clear();
+    P.big.clear();
+}
+
+// Whether the grouped kernels can take a domain: lines of at most
+// kMaxBatchLine voxels (K = 512 / 16 segments of at most 16 elements), an
+// [n][S] coefficient table of at most kBatchTab entries per axis (staged in
+// LDS), at most kMaxBatchSub substrates (the reverse step's per-substrate
+// sums are kept in LDS) and 32-bit element offsets.
+bool group_fits(bfvm_grid g)
+{
+    for (int a = 0; a < 3; ++a) {
+        const int64_t n = a == 0 ? g->nx : (a == 1 ? g->ny : g->nz);
+        if (n > kMaxBatchLine || n * g->S > kBatchTab) return false;
+    }
+    return g->S <= kMaxBatchSub && g->nelem() < (1ll << 31);
 }
 
 }  // namespace
@@ -490,10 +515,12 @@ struct bfvm_batch_s {
     std::vector<BDomain> doms;        // host copy of the descriptors
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    // side streams and events of the per-storage-type chains (grouped mode)
-    hipStream_t side[2] = {nullptr, nullptr};
+    // side streams and events of the per-storage-type chains (grouped mode);
+    // side[2] carries the members the grouped kernels cannot take
+    hipStream_t side[3] = {nullptr, nullptr, nullptr};
     hipEvent_t ev_fork = nullptr;
-    hipEvent_t ev_join[2] = {nullptr, nullptr};
+    hipEvent_t ev_join[3] = {nullptr, nullptr, nullptr};
+    std::vector<uint8_t> large;       // 1: member runs its own grid's launches
     int mode = BFVM_BATCH_GROUPED;
     BDomain* d_doms = nullptr;
     int64_t chunk_elems = 1 << 14;    // work per item
@@ -582,9 +609,11 @@ int build_forward(bfvm_batch b)
     // adjoint program is rebuilt on its next call as well
     free_program(b->adj);
     b->adj_subset.clear();
-    std::vector<int32_t> all(b->doms.size());
-    for (size_t i = 0; i < all.size(); ++i) all[i] = (int32_t)i;
-    build_program(b, all, forward_program(), b->fwd);
+    std::vector<int32_t> small, big;
+    for (size_t i = 0; i < b->doms.size(); ++i) (b->large[i] ? big : small).push_back((int32_t)i);
+    build_program(b, small, forward_program(), b->fwd);
+    b->fwd.big = big;
+    b->fwd.reverse = false;
     return upload_program(b, b->fwd);
 }
 
@@ -603,6 +632,7 @@ void launch_group_sweep(int M, int64_t n, hipStream_t s, const BDomain* d, const
 int enqueue_program(bfvm_batch b, const Program& P)
 {
     if (b->mode == BFVM_BATCH_PERSISTENT) {
+        if (!P.big.empty()) return bfail(BFVM_ESTATE, "the persistent mode takes no members beyond the grouped limits");
         const int64_t nreset = 2 + P.ncounters;
         hipLaunchKernelGGL(k_batch_reset, dim3((unsigned)std::min<int64_t>((nreset + 255) / 256, 1024)), dim3(256),
                            0, b->stream, b->d_counters, nreset);
@@ -623,9 +653,26 @@ int enqueue_program(bfvm_batch b, const Program& P)
     for (const Launch& L : P.launches)
         if (chain_of[L.dtype] < 0) chain_of[L.dtype] = nchain++;
     const hipStream_t cs[3] = {b->stream, b->side[0], b->side[1]};
-    if (nchain > 1) {
-        BHIP(hipEventRecord(b->ev_fork, b->stream), "fork event");
-        for (int c = 1; c < nchain; ++c) BHIP(hipStreamWaitEvent(cs[c], b->ev_fork, 0), "fork wait");
+    const bool big = !P.big.empty();
+    if (nchain > 1 || big) BHIP(hipEventRecord(b->ev_fork, b->stream), "fork event");
+    for (int c = 1; c < nchain; ++c) BHIP(hipStreamWaitEvent(cs[c], b->ev_fork, 0), "fork wait");
+    // Members beyond the grouped kernels' limits run their own grid's
+    // kernels (plain schedule, the grid's plans), one after another on a
+    // chain of their own beside the grouped chains.
+    if (big) {
+        BHIP(hipStreamWaitEvent(b->side[2], b->ev_fork, 0), "fork wait");
+        for (int32_t i : P.big) {
+            bfvm_grid g = b->grids[i];
+            const BDomain& d = b->doms[i];
+            int st;
+            if (!P.reverse) {
+                st = enqueue_step(g, d.buf[0], b->side[2]);
+            } else {
+                OnStream on(g, b->side[2]);
+                st = adjoint_enqueue(g, d.buf[0], d.buf[1], g->work, g->red_partials, g->red_out);
+            }
+            if (st) return st;
+        }
     }
     for (const Launch& L : P.launches) {
         const BItem* it = P.d_items + L.off;
@@ -648,6 +695,10 @@ int enqueue_program(bfvm_batch b, const Program& P)
     for (int c = 1; c < nchain; ++c) {
         BHIP(hipEventRecord(b->ev_join[c - 1], cs[c]), "join event");
         BHIP(hipStreamWaitEvent(b->stream, b->ev_join[c - 1], 0), "join wait");
+    }
+    if (big) {
+        BHIP(hipEventRecord(b->ev_join[2], b->side[2]), "join event");
+        BHIP(hipStreamWaitEvent(b->stream, b->ev_join[2], 0), "join wait");
     }
     return BFVM_OK;
 }
@@ -740,15 +791,12 @@ int bfvm_batch_create(bfvm_batch* out, int32_t ndomains, const bfvm_grid* grids,
     for (int32_t i = 0; i < ndomains; ++i) {
         if (!grids[i] || !fields[i]) return bfail(BFVM_EINVAL, "NULL grid or field");
         if (!grids[i]->have_params) return bfail(BFVM_ESTATE, "every grid needs set_params first");
-        for (int a = 0; a < 3; ++a) {
-            const int64_t n = a == 0 ? grids[i]->nx : (a == 1 ? grids[i]->ny : grids[i]->nz);
-            if (n > kMaxBatchLine) return bfail(BFVM_EINVAL, "batched domains support line lengths up to 256");
-            if (n * grids[i]->S > kBatchTab)
-                return bfail(BFVM_EINVAL, "batched domains support line length x substrates up to 2048");
-        }
-        if (grids[i]->S > kMaxBatchSub) return bfail(BFVM_EINVAL, "batched domains support up to 256 substrates");
-        // (implied by the two limits above: the kernels use 32-bit element offsets)
-        if (grids[i]->nelem() >= (1ll << 31)) return bfail(BFVM_EINVAL, "batched domain too large");
+        // a member beyond the grouped limits runs with its grid's own
+        // reverse-step workspace, so that grid may hold one member only
+        if (!group_fits(grids[i]))
+            for (int32_t j = 0; j < ndomains; ++j)
+                if (j != i && grids[j] == grids[i])
+                    return bfail(BFVM_EINVAL, "a grid beyond the grouped limits appears twice in the batch");
     }
     bfvm_batch b = new (std::nothrow) bfvm_batch_s();
     if (!b) return bfail(BFVM_ENOMEM, "host allocation failed");
@@ -760,7 +808,7 @@ int bfvm_batch_create(bfvm_batch* out, int32_t ndomains, const bfvm_grid* grids,
         }
         b->own_stream = true;
     }
-    for (int c = 0; c < 2; ++c) {   // default priority, like the batch stream
+    for (int c = 0; c < 3; ++c) {   // default priority, like the batch stream
         if (hipStreamCreateWithFlags(&b->side[c], hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&b->ev_join[c], hipEventDisableTiming) != hipSuccess) {
             bfvm_batch_destroy(b);
@@ -773,6 +821,8 @@ int bfvm_batch_create(bfvm_batch* out, int32_t ndomains, const bfvm_grid* grids,
     }
     b->grids.assign(grids, grids + ndomains);
     b->gens.assign(ndomains, 0);
+    b->large.resize(ndomains);
+    for (int32_t i = 0; i < ndomains; ++i) b->large[i] = group_fits(grids[i]) ? 0 : 1;
     b->doms.resize(ndomains);
     std::memset(b->doms.data(), 0, sizeof(BDomain) * ndomains);
     refresh_from_grids(b);
@@ -813,7 +863,7 @@ int bfvm_batch_destroy(bfvm_batch b)
     if (b->d_partials) (void)hipFree(b->d_partials);
     // d_counters is a slice of the uncached pool: never freed
     if (b->work_mem) (void)hipFree(b->work_mem);
-    for (int c = 0; c < 2; ++c) {
+    for (int c = 0; c < 3; ++c) {
         if (b->side[c]) {
             (void)hipStreamSynchronize(b->side[c]);
             (void)hipStreamDestroy(b->side[c]);
@@ -846,7 +896,18 @@ int bfvm_batch_set_fields(bfvm_batch b, int32_t which, void* const* ptrs)
     if ((which != 0 && which != 1) || !ptrs) return bfail(BFVM_EINVAL, "which must be 0 (field) or 1 (gradient)");
     for (size_t i = 0; i < b->doms.size(); ++i)
         if (which == 0 && !ptrs[i]) return bfail(BFVM_EINVAL, "NULL field");
-    for (size_t i = 0; i < b->doms.size(); ++i) b->doms[i].buf[which] = ptrs[i];
+    // the grouped kernels read the pointers from the device descriptors;
+    // the launches of members beyond the grouped limits carry them as
+    // kernel arguments, so their graphs are captured again
+    bool recapture = false;
+    for (size_t i = 0; i < b->doms.size(); ++i) {
+        recapture |= b->large[i] && b->doms[i].buf[which] != ptrs[i];
+        b->doms[i].buf[which] = ptrs[i];
+    }
+    if (recapture) {
+        drop_graph(b->fwd);
+        drop_graph(b->adj);
+    }
     return upload_doms(b);
 }
 
@@ -884,28 +945,36 @@ int bfvm_batch_step_adjoint(bfvm_batch b, int32_t count, const int32_t* subset, 
     }
     if (int st = sync_grids(b)) return st;
     std::vector<int32_t> sub(subset, subset + count);
-    if (sub != b->adj_subset || !b->adj.exec) {
-        // (re)build the adjoint program: workspace, items, partials, graph
+    if (sub != b->adj_subset) {
+        // (re)build the adjoint program: workspace, items, partials, graph.
+        // Members beyond the grouped limits run their grid's own reverse
+        // step, in the grid's own workspace.
         free_program(b->adj);
         b->adj_subset.clear();
         if (b->work_mem) (void)hipFree(b->work_mem);
         b->work_mem = nullptr;
+        std::vector<int32_t> small, big;
+        for (int32_t i : sub) (b->large[i] ? big : small).push_back(i);
+        for (int32_t i : big)
+            if (int st = ensure_adjoint_workspace(b->grids[i])) return st;
         size_t total = 0;
-        std::vector<size_t> off(count);
-        for (int32_t i = 0; i < count; ++i) {
-            const BDomain& d = b->doms[sub[i]];
+        std::vector<size_t> off(small.size());
+        for (size_t i = 0; i < small.size(); ++i) {
+            const BDomain& d = b->doms[small[i]];
             off[i] = total;
             total += 3 * (size_t)(d.nx * d.ny * d.nz * d.S) * dtype_size(d.dtype);
             total = (total + 255) & ~(size_t)255;
         }
-        BHIP(hipMalloc(&b->work_mem, total), "hipMalloc adjoint workspace");
-        for (int32_t i = 0; i < count; ++i) {
-            BDomain& d = b->doms[sub[i]];
+        if (total) BHIP(hipMalloc(&b->work_mem, total), "hipMalloc adjoint workspace");
+        for (size_t i = 0; i < small.size(); ++i) {
+            BDomain& d = b->doms[small[i]];
             const size_t nb = (size_t)(d.nx * d.ny * d.nz * d.S) * dtype_size(d.dtype);
             for (int k = 0; k < 3; ++k) d.buf[2 + k] = static_cast<char*>(b->work_mem) + off[i] + k * nb;
         }
         if (int st = upload_doms(b)) return st;
-        build_program(b, sub, adjoint_program(), b->adj);
+        build_program(b, small, adjoint_program(), b->adj);
+        b->adj.big = big;
+        b->adj.reverse = true;
         if (b->partials_cap < b->adj.npartials) {
             drop_graph(b->fwd);   // the forward graph holds the old partials pointer
             if (b->d_partials) (void)hipFree(b->d_partials);
@@ -915,9 +984,10 @@ int bfvm_batch_step_adjoint(bfvm_batch b, int32_t count, const int32_t* subset, 
             b->partials_cap = b->adj.npartials;
         }
         if (int st = upload_program(b, b->adj)) return st;
-        if (int st = capture(b, b->adj)) return st;
         b->adj_subset = sub;
     }
+    if (!b->adj.exec)
+        if (int st = capture(b, b->adj)) return st;
     BHIP(hipGraphLaunch(b->adj.exec, b->stream), "graph launch");
     if (int st = finish(b)) return st;
     std::vector<double> part(b->adj.npartials);
@@ -945,6 +1015,12 @@ int bfvm_batch_step_adjoint(bfvm_batch b, int32_t count, const int32_t* subset, 
     }
     for (int32_t i = 0; i < count; ++i) {
         bfvm_grid g = b->grids[sub[i]];
+        if (b->large[sub[i]]) {
+            // the grid's own reverse step left its sums in its red_out
+            if (int st = adjoint_accumulate(g, g->red_out, b->stream, grad_D + first[i], grad_lambda + first[i]))
+                return st;
+            continue;
+        }
         for (int s = 0; s < g->S; ++s)
             for (int a = 0; a < 3; ++a) {
                 grad_D[first[i] + s] += -Gr[(first[i] + s) * 3 + a] * g->dt / (g->h[a] * g->h[a]);
@@ -959,6 +1035,8 @@ int bfvm_batch_get_plan(bfvm_batch b, int32_t domain, int32_t axis, int32_t* m, 
     if (!b || !m || !lpw) return bfail(BFVM_EINVAL, "NULL");
     if (domain < 0 || domain >= (int32_t)b->doms.size() || axis < 0 || axis > 2)
         return bfail(BFVM_ERANGE, "domain or axis");
+    if (b->large[domain])
+        return bfail(BFVM_ESTATE, "the domain runs its own grid's kernels: query its plan with bfvm_get_plan");
     *m = b->doms[domain].M[axis];
     *lpw = b->doms[domain].lpw[axis];
     return BFVM_OK;
@@ -969,6 +1047,8 @@ int bfvm_batch_set_plan(bfvm_batch b, int32_t domain, int32_t axis, int32_t m, i
     if (!b) return bfail(BFVM_EINVAL, "batch is NULL");
     if (domain < 0 || domain >= (int32_t)b->doms.size() || axis < 0 || axis > 2)
         return bfail(BFVM_ERANGE, "domain or axis");
+    if (b->large[domain])
+        return bfail(BFVM_ESTATE, "the domain runs its own grid's kernels: set its plan with bfvm_set_plan");
     if (m != 4 && m != 8 && m != 16) return bfail(BFVM_EINVAL, "m must be 4, 8 or 16");
     if (m > max_m_for_mode(b->mode)) return bfail(BFVM_EINVAL, "m too large for the batch mode");
     if (lpw != 16 && lpw != 32 && lpw != 64) return bfail(BFVM_EINVAL, "lpw must be 16, 32 or 64");
@@ -1102,15 +1182,17 @@ extern "C" int bfvm_batch_autotune(bfvm_batch b, const char* cache_path, double*
     int st = BFVM_OK;
     if (cache_path && load_cache(cache_path, arch, &chunk, &cached)) {
         bool all = true;
-        for (auto& d : b->doms)
-            for (int a = 0; a < 3; ++a) {
+        for (size_t i = 0; i < b->doms.size(); ++i)
+            for (int a = 0; a < 3 && !b->large[i]; ++a) {
+                const BDomain& d = b->doms[i];
                 auto it = cached.find(class_key(d, a));
                 if (it == cached.end() || !plan_ok(b->mode, axis_len(d, a), it->second.first, it->second.second))
                     all = false;
             }
         if (all) {
-            for (auto& d : b->doms)
-                for (int a = 0; a < 3; ++a) {
+            for (size_t i = 0; i < b->doms.size(); ++i)
+                for (int a = 0; a < 3 && !b->large[i]; ++a) {
+                    BDomain& d = b->doms[i];
                     const auto pl = cached[class_key(d, a)];
                     d.M[a] = pl.first;
                     d.lpw[a] = pl.second;
@@ -1129,7 +1211,9 @@ extern "C" int bfvm_batch_autotune(bfvm_batch b, const char* cache_path, double*
         std::vector<BDomain> keep = b->doms;
         for (int l : lps) {
             std::vector<BDomain> trial = keep;
-            for (auto& d : trial) {
+            for (size_t i = 0; i < trial.size(); ++i) {
+                if (b->large[i]) continue;
+                BDomain& d = trial[i];
                 const int m = smallest_m(axis_len(d, a), l, max_m_for_mode(b->mode));
                 if (m) {
                     d.M[a] = m;
@@ -1162,8 +1246,8 @@ extern "C" int bfvm_batch_autotune(bfvm_batch b, const char* cache_path, double*
     b->chunk_elems = best_chunk;
     if ((st = upload_doms(b)) || (st = build_forward(b))) return st;
     if (cache_path) {
-        for (auto& d : b->doms)
-            for (int a = 0; a < 3; ++a) cached[class_key(d, a)] = {d.M[a], d.lpw[a]};
+        for (size_t i = 0; i < b->doms.size(); ++i)
+            for (int a = 0; a < 3 && !b->large[i]; ++a) cached[class_key(b->doms[i], a)] = {b->doms[i].M[a], b->doms[i].lpw[a]};
         save_cache(cache_path, arch, best_chunk, cached);
     }
     *best_ms = best;

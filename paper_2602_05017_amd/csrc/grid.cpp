@@ -381,13 +381,54 @@ int64_t adjoint_partials_count(bfvm_grid g)
     return n;
 }
 
-// One reverse step into caller-provided workspace: work[3] field buffers,
-// partials (adjoint_partials_count doubles), red_out (6 S doubles).
-// Enqueues on the grid's stream, then reads the reductions back in chunks
-// of substrates through a stack buffer and increments grad_D, grad_lambda.
-// Allocates nothing.
-int adjoint_step_into(bfvm_grid g, const void* field_in, void* grad, void* const work[3], double* partials,
-                      double* red_out, double* grad_D, double* grad_lambda)
+// One plain-schedule step (source, then Dirichlet and a sweep per axis, then
+// Dirichlet) on the grid's stream.
+int run_plain_step(bfvm_grid g, void* field)
+{
+    int st;
+    if ((st = run_source(g, field))) return st;
+    for (int a = 0; a < 3; ++a) {
+        if ((st = run_dirichlet(g, field))) return st;
+        if ((st = run_sweep(g, a, field, field, false))) return st;
+    }
+    return run_dirichlet(g, field);
+}
+
+int enqueue_step(bfvm_grid g, void* field, hipStream_t s)
+{
+    OnStream on(g, s);
+    return run_plain_step(g, field);
+}
+
+int ensure_adjoint_workspace(bfvm_grid g)
+{
+    const size_t bytes = (size_t)g->nelem() * dtype_size(g->dtype);
+    for (int a = 0; a < 3; ++a) {
+        if (!g->work[a]) {
+            hipError_t e = hipMalloc(&g->work[a], bytes);
+            if (e != hipSuccess) {
+                g->work[a] = nullptr;
+                return fail(BFVM_ENOMEM, std::string("adjoint workspace: ") + hipGetErrorString(e));
+            }
+        }
+    }
+    // per-line sums of the three axes side by side, summed by one final launch
+    const int64_t np = adjoint_partials_count(g);
+    if (!g->red_partials || g->red_count < np) {
+        dfree(g->red_partials);
+        HIP_TRY(hipMalloc((void**)&g->red_partials, sizeof(double) * np), "hipMalloc partials");
+        g->red_count = np;
+    }
+    if (!g->red_out) HIP_TRY(hipMalloc((void**)&g->red_out, sizeof(double) * 2 * g->S * 3), "hipMalloc red_out");
+    return BFVM_OK;
+}
+
+// The device part of one reverse step, enqueued on the grid's stream into
+// caller-provided workspace: work[3] field buffers, partials
+// (adjoint_partials_count doubles), red_out (6 S doubles, see
+// adjoint_accumulate).  Allocates nothing and never waits for the device.
+int adjoint_enqueue(bfvm_grid g, const void* field_in, void* grad, void* const work[3], double* partials,
+                    double* red_out)
 {
     const size_t bytes = (size_t)g->nelem() * dtype_size(g->dtype);
     const int S = g->S;
@@ -441,8 +482,17 @@ int adjoint_step_into(bfvm_grid g, const void* field_in, void* grad, void* const
     if (e != hipSuccess) return hip_fail(e, "mask kernel");
     e = launch_source_transpose(g->dtype, grad, g->src_vox, g->src_invQ, g->nsrc, S, st);
     if (e != hipSuccess) return hip_fail(e, "source transpose kernel");
-    // red_out[(a*S + s)*2 + {0, 1}]: sums of y^T (L_N x) and y^T x.
-    // dL/dr_a = -sum y^T L_N x, dL/dbeta = -sum y^T x; dr_a/dD = dt/h_a^2, dbeta/dlambda = dt/3
+    return BFVM_OK;
+}
+
+// Reads red_out[(a*S + s)*2 + {0, 1}], the sums of y^T (L_N x) and y^T x, in
+// chunks of substrates through a stack buffer (after the work before it on
+// stream st) and adds dL/dD and dL/dlambda into grad_D, grad_lambda:
+// dL/dr_a = -sum y^T L_N x, dL/dbeta = -sum y^T x, dr_a/dD = dt/h_a^2 and
+// dbeta/dlambda = dt/3.  Allocates nothing.
+int adjoint_accumulate(bfvm_grid g, const double* red_out, hipStream_t st, double* grad_D, double* grad_lambda)
+{
+    const int S = g->S;
     constexpr int kChunk = 64;
     double buf[3][2 * kChunk];
     for (int s0 = 0; s0 < S; s0 += kChunk) {
@@ -459,6 +509,13 @@ int adjoint_step_into(bfvm_grid g, const void* field_in, void* grad, void* const
             }
     }
     return BFVM_OK;
+}
+
+int adjoint_step_into(bfvm_grid g, const void* field_in, void* grad, void* const work[3], double* partials,
+                      double* red_out, double* grad_D, double* grad_lambda)
+{
+    if (int rc = adjoint_enqueue(g, field_in, grad, work, partials, red_out)) return rc;
+    return adjoint_accumulate(g, red_out, g->stream, grad_D, grad_lambda);
 }
 
 }  // namespace bfvm
@@ -707,15 +764,8 @@ int bfvm_step(bfvm_grid g, void* field, int64_t nsteps)
             if (int st = sched == 1 ? run_step_fused(g, field, w) : run_step_zfused(g, field, w)) return st;
         return BFVM_OK;
     }
-    for (int64_t t = 0; t < nsteps; ++t) {
-        int st;
-        if ((st = run_source(g, field))) return st;
-        for (int a = 0; a < 3; ++a) {
-            if ((st = run_dirichlet(g, field))) return st;
-            if ((st = run_sweep(g, a, field, field, false))) return st;
-        }
-        if ((st = run_dirichlet(g, field))) return st;
-    }
+    for (int64_t t = 0; t < nsteps; ++t)
+        if (int st = bfvm::run_plain_step(g, field)) return st;
     return BFVM_OK;
 }
 
@@ -733,26 +783,8 @@ int bfvm_step_adjoint(bfvm_grid g, const void* field_in, void* grad, double* gra
     if (int st = check_grid(g)) return st;
     if (!field_in || !grad || !grad_D || !grad_lambda) return fail(BFVM_EINVAL, "NULL pointer");
     if (!g->have_params) return fail(BFVM_ESTATE, "set_params must come before step_adjoint");
-    const size_t bytes = (size_t)g->nelem() * dtype_size(g->dtype);
-    const int S = g->S;
     // workspace: three sweep outputs, reduction partials and results
-    for (int a = 0; a < 3; ++a) {
-        if (!g->work[a]) {
-            hipError_t e = hipMalloc(&g->work[a], bytes);
-            if (e != hipSuccess) {
-                g->work[a] = nullptr;
-                return fail(BFVM_ENOMEM, std::string("adjoint workspace: ") + hipGetErrorString(e));
-            }
-        }
-    }
-    // per-line sums of the three axes side by side, summed by one final launch
-    const int64_t np = bfvm::adjoint_partials_count(g);
-    if (!g->red_partials || g->red_count < np) {
-        dfree(g->red_partials);
-        HIP_TRY(hipMalloc((void**)&g->red_partials, sizeof(double) * np), "hipMalloc partials");
-        g->red_count = np;
-    }
-    if (!g->red_out) HIP_TRY(hipMalloc((void**)&g->red_out, sizeof(double) * 2 * S * 3), "hipMalloc red_out");
+    if (int st = bfvm::ensure_adjoint_workspace(g)) return st;
     return bfvm::adjoint_step_into(g, field_in, grad, g->work, g->red_partials, g->red_out, grad_D, grad_lambda);
 }
 

@@ -118,10 +118,22 @@ struct bfvm_grid_s;
 
 namespace bfvm {
 // One reverse step (bfvm_step_adjoint) into caller-provided workspace, shared
-// by the allocating and the allocation-free entry points (grid.cpp).
+// by the allocating and the allocation-free entry points (grid.cpp):
+// adjoint_enqueue puts the device work on the grid's stream,
+// adjoint_accumulate reads the parameter sums back and adds them to the
+// caller's gradients, adjoint_step_into does both.
 int64_t adjoint_partials_count(bfvm_grid_s* g);
+int adjoint_enqueue(bfvm_grid_s* g, const void* field_in, void* grad, void* const work[3], double* partials,
+                    double* red_out);
+int adjoint_accumulate(bfvm_grid_s* g, const double* red_out, hipStream_t st, double* grad_D, double* grad_lambda);
 int adjoint_step_into(bfvm_grid_s* g, const void* field_in, void* grad, void* const work[3], double* partials,
                       double* red_out, double* grad_D, double* grad_lambda);
+// the grid's own reverse-step workspace (work, red_partials, red_out),
+// allocated on first use
+int ensure_adjoint_workspace(bfvm_grid_s* g);
+// one step of the plain schedule on the grid's stream / on stream s
+int run_plain_step(bfvm_grid_s* g, void* field);
+int enqueue_step(bfvm_grid_s* g, void* field, hipStream_t s);
 }  // namespace bfvm
 
 // --------------------------------------------------------------- grid object
@@ -204,3 +216,27 @@ struct bfvm_grid_s {
     int64_t nvox() const { return nx * ny * nz; }
     int64_t nelem() const { return nx * ny * nz * (int64_t)S; }
 };
+
+namespace bfvm {
+// While alive, the grid's stage launches go to stream s with its stage
+// timers off (a batch enqueues the members its grouped kernels cannot take
+// this way, on one of its own streams); the grid's stream and timers are
+// restored on destruction.
+struct OnStream {
+    bfvm_grid_s* g;
+    hipStream_t keep;
+    bool timing;
+    OnStream(bfvm_grid_s* g_, hipStream_t s) : g(g_), keep(g_->stream), timing(g_->timing)
+    {
+        g->stream = s;
+        g->timing = false;
+    }
+    ~OnStream()
+    {
+        g->stream = keep;
+        g->timing = timing;
+    }
+    OnStream(const OnStream&) = delete;
+    OnStream& operator=(const OnStream&) = delete;
+};
+}  // namespace bfvm

@@ -26,8 +26,8 @@ import pytest
 
 import oracle
 import workloads
-from gpu_helpers import (make_grid, one_substrate, oracle_adjoint, oracle_lists, param_grad_bars, rel_err, rel_vec,
-                         upload)
+from gpu_helpers import (make_grid, one_substrate, oracle_adjoint, oracle_lists, oracle_run, param_grad_bars, rel_err,
+                         rel_vec, small_problem, upload)
 
 pytestmark = pytest.mark.gpu
 
@@ -375,16 +375,94 @@ def test_full_batch_workload_autotuned_100_steps():
     print(f"96 domains vs single-grid runs, 100 steps: worst e_max {worst}")
 
 
-def test_batch_rejects_tables_too_large_for_lds():
-    import paper_2602_05017_amd as bf
-    g = bf.Grid(256, 24, 24, 9, (10.0, 10.0, 10.0), dtype="f64")   # 256 x 9 > 2048 on x
-    g.set_params(np.full(9, 1e3), np.full(9, 0.1), 0.01)
+def test_batch_with_members_beyond_the_grouped_limits():
+    # members the grouped kernels cannot take (a 300-voxel x line; a z axis of
+    # 40 voxels x 64 substrates = 2560 table entries; a 270-voxel y line with
+    # FP32 arithmetic) run their own grid's kernels inside the batch's graph,
+    # beside grouped members: every domain follows the oracle, the graph
+    # equals eager launches, a member beyond the limits equals its own grid's
+    # bfvm_step exactly (the same kernels), and the reverse step of a subset
+    # mixing both kinds matches the oracle's adjoint
     import torch
-    u = torch.zeros((24, 24, 256, 9), dtype=torch.float64, device="cuda")
+    import paper_2602_05017_amd as bf
+    small = _domains(3, lo=24, hi=48, nsteps=3, seed=1021)
+    big = []
+    for k, (shape, S, dtype, ndir) in enumerate((((300, 20, 16), 2, "f64", 9), ((24, 20, 40), 64, "f32", 0),
+                                                  ((16, 270, 12), 3, "f32fast", 0))):
+        q = small_problem(shape, S, 1030 + k, nsrc=30, ndir=ndir, nsteps=3)
+        q.dtype = dtype
+        big.append(q)
+    probs = [small[0], big[0], small[1], big[1], big[2], small[2]]
+    large = {1, 3, 4}
+    grids, fields = _setup(probs)
+    start = [f.clone() for f in fields]
+    b = bf.Batch(grids, fields)
+    for i in large:
+        with pytest.raises(bf.BfvmError) as ei:
+            b.plan(i, 0)
+        assert ei.value.code == "ESTATE"
+    b.step(3)
+    torch.cuda.synchronize()
+    for i, (p, g, f) in enumerate(zip(probs, grids, fields)):
+        e = rel_err(g.read_field(f), oracle_run(p, 3))[0]
+        print(f"{p.name} {p.dtype} {p.nx}x{p.ny}x{p.nz}x{p.S} {'own kernels' if i in large else 'grouped'}: "
+              f"3 steps vs oracle e_max {e:.2e}")
+        assert e <= TOL[p.dtype], (i, p.dtype, e)
+    eager = [x.clone() for x in start]
+    b2 = bf.Batch(grids, eager)
+    b2.step(3, graph=False)
+    torch.cuda.synchronize()
+    assert all(torch.equal(x, f) for x, f in zip(eager, fields))
+    b2.close()
+    for i in large:
+        own = start[i].clone()
+        grids[i].step(own, 3)
+        torch.cuda.synchronize()
+        assert torch.equal(own, fields[i]), i
+    # a grid beyond the limits may hold one member only
     with pytest.raises(bf.BfvmError) as ei:
-        bf.Batch([g], [u])
+        bf.Batch([grids[1], grids[1]], [fields[1], start[1]])
     assert ei.value.code == "EINVAL"
-    g.close()
+    # reverse step of a subset with grouped and own-kernel members
+    rng = np.random.default_rng(21)
+    gin = [(rng.random(p.shape) - 0.5).astype(np.float64 if p.dtype == "f64" else np.float32) for p in probs]
+    grads = [torch.from_numpy(x.copy()).to("cuda") for x in gin]
+    b.set_grads(grads)
+    subset = [3, 0, 1, 4, 5]
+    gD, gL = b.step_adjoint(subset)
+    torch.cuda.synchronize()
+    off = 0
+    for i in subset:
+        p = probs[i]
+        e = _check_adjoint_vs_oracle(p, grids[i].read_field(fields[i]), gin[i], grads[i].double().cpu().numpy(),
+                                     gD[off:off + p.S], gL[off:off + p.S])
+        print(f"{p.name} {p.dtype} reverse step vs oracle: grad {e[0]:.2e}, dD at {e[1]:.2f} and dlambda at "
+              f"{e[2]:.2f} of their bars")
+        off += p.S
+    assert torch.equal(grads[2], torch.from_numpy(gin[2]).to("cuda"))   # outside the subset
+    # new gradient buffers (the graph is captured again for the members
+    # whose launches carry their pointers): the same sums from the same
+    # gradients, and the previous buffers are left alone
+    kept = [g.clone() for g in grads]
+    fresh = [torch.from_numpy(x.copy()).to("cuda") for x in gin]
+    b.set_grads(fresh)
+    gD2, gL2 = b.step_adjoint(subset)
+    assert np.array_equal(gD2, gD) and np.array_equal(gL2, gL)
+    assert all(torch.equal(x, y) for x, y in zip(grads, kept))
+    assert all(torch.equal(fresh[i], grads[i]) for i in subset)
+    # new field buffers for the forward graph likewise
+    before = [f.clone() for f in fields]
+    moved = [f.clone() for f in fields]
+    b.set_fields(moved)
+    b.step(1)
+    torch.cuda.synchronize()
+    assert all(torch.equal(f, f0) for f, f0 in zip(fields, before))
+    for i in large:
+        own = before[i].clone()
+        grids[i].step(own, 1)
+        torch.cuda.synchronize()
+        assert torch.equal(own, moved[i]), i
+    b.close()
 
 
 def test_batch_follows_member_grid_changes():

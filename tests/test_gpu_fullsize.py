@@ -3,10 +3,10 @@ configuration the benchmark times (default plans).
 
 - DCT-II eigenmode at full size: every sampled element must match the closed
   form u0 * prod_a mu_a^-m (a property that holds at any size).
-- The benchmarked run (1e6 source/sink voxels, 20 steps): the substrates
-  with the smallest and the largest D are compared element by element with
-  the FP64 oracle (substrates do not couple, so the oracle runs each alone),
-  for FP64 storage and both FP32 forms.
+- The benchmarked run (1e6 source/sink voxels, 20 steps): every substrate
+  is compared element by element with the FP64 oracle (substrates do not
+  couple, so the oracle runs each alone), for FP64 storage and both FP32
+  forms.
 """
 import gc
 
@@ -121,7 +121,7 @@ def _one_substrate_reference(p, s, nsteps):
         src = oracle.Sources(p.src.voxel, p.src.secretion[:, s:s + 1], p.src.saturation[:, s:s + 1],
                              p.src.uptake[:, s:s + 1])
         oracle.step(u, p.h, p.D[s:s + 1], p.lam[s:s + 1], p.dt, src, None, nsteps)
-        if len(_REF) >= 2:
+        if len(_REF) >= p.S:
             _REF.clear()
         _REF[key] = u[..., 0]
     return _REF[key]
@@ -131,28 +131,30 @@ def _one_substrate_reference(p, s, nsteps):
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5), ("f32fast", 1e-5)])
 def test_tumour_scale_20_steps_vs_oracle(dtype, tol):
     # the benchmark's workload and launch configuration (default plans, 20
-    # steps), each storage form against the oracle; substrates do not couple,
-    # so the oracle runs the substrates with the smallest and the largest D
-    # (smallest and largest r: the two ends of the conditioning) alone, over
-    # every element of their fields.  FP32 arithmetic: r <= 2.8 here, where
-    # its measured error is 2.5e-6 after 20 steps, inside the FP32 bar
+    # steps), each storage form against the oracle over every element of
+    # every substrate; substrates do not couple, so the oracle runs each
+    # alone.  The four 8 GB FP64 references are kept for the next storage
+    # form (32 GB of host memory).  FP32 arithmetic: r <= 2.8 here, where its
+    # measured error is 2.5e-6 after 20 steps, inside the FP32 bar
     import torch
     p = workloads.config(3)
     assert p.nsteps == 20
-    subs = [int(np.argmin(p.D)), int(np.argmax(p.D))]
     g = make_grid(p, dtype)
     u = torch.from_numpy(p.u0).to(device="cuda", dtype=g.torch_dtype)
     g.step(u, p.nsteps)
     torch.cuda.synchronize()
-    got = {s: u[..., s].cpu().numpy() for s in subs}
     g.close()
+    worst = 0.0
+    for s in range(p.S):
+        got = u[..., s].cpu().numpy()
+        ref = _one_substrate_reference(p, s, p.nsteps)
+        emax, e2 = rel_err(got[..., None], ref[..., None])
+        del got
+        print(f"1000^3x4 {dtype}, substrate {s} (D={p.D[s]:.3g}), {p.nsteps} steps: e_max={emax:.3e} e_2={e2:.3e}")
+        worst = max(worst, emax)
     del u
     _free()
-    for s in subs:
-        ref = _one_substrate_reference(p, s, p.nsteps)
-        emax, e2 = rel_err(got[s][..., None], ref[..., None])
-        print(f"1000^3x4 {dtype}, substrate {s} (D={p.D[s]:.3g}), {p.nsteps} steps: e_max={emax:.3e} e_2={e2:.3e}")
-        assert emax <= tol
+    assert worst <= tol
 
 
 def test_endtoend_pipeline_matches_oracle():
