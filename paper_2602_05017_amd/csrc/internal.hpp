@@ -42,7 +42,14 @@ AxisGeom slab_geom(int axis, int64_t nx, int64_t ny, int64_t nz, int32_t S, int6
 AxisGeom zslab_geom(int axis, int64_t nx, int64_t ny, int64_t nz, int32_t S, int64_t z0, int64_t z1);
 
 // Launch plan of one sweep (see bfvm_get_plan in bfvm.h).
-enum PlanKind { PLAN_LINE = 0, PLAN_SEG_STRIDED = 1, PLAN_SEG_XTILE = 2, PLAN_SEG_XROWS = 3, PLAN_SEG_XPIPE = 4 };
+enum PlanKind {
+    PLAN_LINE = 0,
+    PLAN_SEG_STRIDED = 1,
+    PLAN_SEG_XTILE = 2,
+    PLAN_SEG_XROWS = 3,
+    PLAN_SEG_XPIPE = 4,
+    PLAN_SEG_HALVES = 5
+};
 
 struct SweepPlan {
     int32_t kind = PLAN_LINE;

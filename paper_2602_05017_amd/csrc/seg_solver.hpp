@@ -20,10 +20,13 @@ namespace bfvm {
 // incoming carry in place of its local value (or, where it fits, by the
 // lane-parallel scan below).
 
+// init: the carry entering the first segment in scan order; last (if not
+// null): where the carry leaving the last segment is written, at last[line].
 template <typename C>
-__device__ __forceinline__ void carry_scan(C* val, const C* prod, int K, int nl, int line, bool reverse)
+__device__ __forceinline__ void carry_scan(C* val, const C* prod, int K, int nl, int line, bool reverse,
+                                           C init = 0, C* last = nullptr)
 {
-    C c = 0;
+    C c = init;
     if (!reverse) {
         int j = 0;
         for (; j + 8 <= K; j += 8) {
@@ -53,6 +56,7 @@ __device__ __forceinline__ void carry_scan(C* val, const C* prod, int K, int nl,
             c = f + g * c;
         }
     }
+    if (last) last[line] = c;
 }
 
 // Lane-parallel form of the same scan.  When a line's K segments fit one

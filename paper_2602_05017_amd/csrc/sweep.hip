@@ -178,12 +178,14 @@ __device__ __forceinline__ void stage_table(C* tab, const C* __restrict__ invd, 
 // table comp ([s][H + 2]: head slots, interior constant, last slot): the nh
 // segments that overlap the head, one row of the interior constant (shared
 // by every other segment before the last slot's), the segment holding slot
-// n - 1, and a zero row for segments past the line end.  Every thread of the
-// block takes part; the caller synchronises before use.
+// n - 1, and a zero row for segments past the line end (left out where no
+// segment lies past it: zero = false).  Every thread of the block takes
+// part; the caller synchronises before use.
 template <int M>
 struct CompRows {
     int nh, tseg, SPr;
-    __device__ __forceinline__ CompRows(int H, int n) : nh((H + M - 1) / M), tseg((n - 1) / M), SPr((nh + 3) * (M + 1)) {}
+    __device__ __forceinline__ CompRows(int H, int n, bool zero = true)
+        : nh((H + M - 1) / M), tseg((n - 1) / M), SPr((nh + 2 + (zero ? 1 : 0)) * (M + 1)) {}
     __device__ __forceinline__ int row(int seg) const
     {
         return seg < nh ? seg : (seg == tseg ? nh + 1 : (seg > tseg ? nh + 2 : nh));
@@ -307,6 +309,187 @@ __global__ __launch_bounds__(1024) void k_sweep_seg_strided(const T* in, T* out,
         line_sums_store<C>(a0, a1, seg, K, line, lpw, sc, false, true, part,
                            (int64_t)by * g.inner + p_first, (int)min((int64_t)lpw, g.inner - p_first));
     }
+}
+
+// ------------------------------------------ kind 5 (y/z, lines in two parts)
+//
+// For lines longer than one block's K = blockDim/lpw segments of M cover
+// (K*M < n <= 2*K*M).  The block takes each line in two parts: a head of
+// K0 = ceil(n/M) - K full segments (h0 = K0*M elements) and a tail of the
+// other n - h0 <= K*M, cut into segments at the same positions as a kind-1
+// block of K0 + K segments would cut the line.  Three passes:
+//   A. head: load, keep a copy in LDS in the storage type, forward
+//      elimination and forward carry scan; the carry leaving the head (the
+//      eliminated value at h0 - 1) is kept per line;
+//   B. tail: load, full solve with that carry entering its forward scan;
+//      the backward carry leaving it (x at h0) is kept per line; store;
+//   C. head again from its LDS copy: the same elimination and forward scan,
+//      then the backward pass with the tail's carry entering it; store.
+// Every element is read from and written to memory once; the head's
+// forward elimination runs twice.  A 512-thread block of this kind leaves
+// room for a second one on the CU, where the kind-1 block of 2K segments
+// (1024 threads) holds a CU alone and the CU issues no loads while it
+// scans.  In passes A and C the segments past the head are idle and pass
+// every carry through unchanged (f = 0, G = 1; bw = 0, GB = 1), so the scans
+// take the same steps, in the same order, as the kind-1 block's.  The
+// backward carry terms reuse the forward carry arrays: a thread reads its
+// own forward carry before it writes its own backward term.  The Thomas
+// constants come from rows built in LDS from the exact compressed table (as
+// in kind 1 with COEF = 2).  Two blocks per CU also need at most 128 VGPRs
+// (4 waves per SIMD): the backward correction is fused with the stores
+// (seg_last_store), which keeps the M = 32 FP64 form at 128 without spills.
+// seg_last fused with the store: each value is stored (slots k < cnt) as
+// soon as its backward correction is added, last slot first
+template <typename T, typename C, int M, typename Coef>
+__device__ __forceinline__ void seg_last_store(const C (&v)[M], C r, const Coef& coef, C X, T* op, int64_t st,
+                                               int cnt)
+{
+    C e = X;
+#pragma unroll
+    for (int k = M - 1; k >= 0; --k) {
+        e = r * coef(k) * e;
+        if (k < cnt) op[k * st] = (T)(v[k] + e);
+    }
+}
+
+template <typename T, typename C, int M, int AX>
+__global__ __launch_bounds__(512, 4) void k_sweep_seg_halves(const T* in, T* out, AxisGeom g,
+                                                          const C* __restrict__ rr, int lpw, int K0,
+                                                          const C* __restrict__ comp, int H)
+{
+    uint32_t bx, by;
+    xcd_tile(bx, by);
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int K = blockDim.x / lpw;
+    const int A = K * lpw;
+    C* sF = reinterpret_cast<C*>(smem);
+    C* sG = sF + A;
+    C* ini = sG + A;   // [line]: forward carry into the tail; [lpw + line]: backward carry into the head
+    C* tab = ini + 2 * lpw;
+    const int n = (int)g.n;
+    // no segment lies past the last slot's: the tail ends with it
+    const CompRows<M> cr(H, n, false);
+    T* raw = reinterpret_cast<T*>(tab + g.S * cr.SPr);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int line = lane % lpw;
+    const int seg = wave * (64 / lpw) + lane / lpw;
+    const int slot = seg * lpw + line;
+    const bool leader = (int)threadIdx.x < lpw;
+    const int64_t p = (int64_t)bx * lpw + line;
+    const bool valid = p < g.inner;
+    const int64_t pa = valid ? p : g.inner - 1;   // clamped line for padding loads
+    const int S = g.S;
+    const int s = (int)((g.p0 + pa) % S);
+    const int64_t st = g.stride;
+    const int64_t line0 = (g.o0 + (int64_t)by) * g.outer_stride + g.p0 + pa;
+    const bool head = seg < K0;
+    const C r = rr[s];
+    build_comp_rows<C, M>(tab, comp, H, n, S, cr);
+    // the coefficient row of global segment gs
+    auto with_coef = [&](int gs, auto&& fn) {
+        const LdsCoef<C> cf{tab + s * cr.SPr + cr.row(gs) * (M + 1), (C)0};
+        fn(cf);
+    };
+    // LDS copy of the head: value k of segment seg in row seg*M + (k ^ (seg & 3))
+    // of lpw values, so that the segments one wave holds use distinct banks
+    auto raw_at = [&](int k) -> T& { return raw[(seg * M + (k ^ (seg & 3))) * lpw + line]; };
+    C v[M];
+    C f, G;
+    // ---- A: head, forward elimination and scan
+    if (head) {
+        const T* ip = in + line0 + (int64_t)seg * M * st;
+        T t[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) t[k] = ip[k * st];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            raw_at(k) = t[k];
+            v[k] = (C)t[k];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < M; ++k) v[k] = (C)0;
+    }
+    __syncthreads();   // the coefficient rows are built
+    with_coef(seg, [&](const auto& cf) { seg_forward<C, M, false>(v, r, cf, f, G); });
+    if (!head) {
+        f = 0;
+        G = 1;
+    }
+    sF[slot] = f;
+    sG[slot] = G;
+    __syncthreads();
+    if (leader) carry_scan(sF, sG, K, lpw, (int)threadIdx.x, false, (C)0, ini);
+    __syncthreads();
+    // ---- B: tail, full solve
+    {
+        const int64_t i0 = (int64_t)K0 * M + (int64_t)seg * M;
+        const int64_t last = g.n - 1 - i0;   // slots k > last are padding
+        const int cnt = !valid || last < 0 ? 0 : (last >= M ? M : (int)last + 1);
+        const int64_t base = line0 + i0 * st;
+#pragma unroll
+        for (int k = 0; k < M; ++k) v[k] = (C)in[base + (k <= last ? k : last) * st];
+        with_coef(K0 + seg, [&](const auto& cf) {
+            seg_forward<C, M, false>(v, r, cf, f, G);
+            sF[slot] = f;
+            sG[slot] = G;
+            __syncthreads();
+            if (leader) carry_scan(sF, sG, K, lpw, (int)threadIdx.x, false, ini[threadIdx.x]);
+            __syncthreads();
+            const C carry = sF[slot];
+            C bw, GB;
+            seg_middle<C, M, false>(v, r, cf, carry, bw, GB);
+            sF[slot] = bw;
+            sG[slot] = GB;
+            __syncthreads();
+            if (leader) carry_scan(sF, sG, K, lpw, (int)threadIdx.x, true, (C)0, ini + lpw);
+            __syncthreads();
+            T* op = out + base;
+            asm volatile("" : "+v"(op));
+            seg_last_store<T, C, M>(v, r, cf, sF[slot], op, st, cnt);
+        });
+    }
+    // ---- C: head again from LDS, full solve with the tail's carry
+    if (head) {
+        // an opaque row pointer: the addresses are recomputed here rather
+        // than kept live from pass A
+        const T* rp = raw + seg * M * lpw + line;
+        asm volatile("" : "+v"(rp));
+#pragma unroll
+        for (int k = 0; k < M; ++k) v[k] = (C)rp[(k ^ (seg & 3)) * lpw];
+    } else {
+#pragma unroll
+        for (int k = 0; k < M; ++k) v[k] = (C)0;
+    }
+    with_coef(seg, [&](const auto& cf) {
+        seg_forward<C, M, false>(v, r, cf, f, G);
+        if (!head) {
+            f = 0;
+            G = 1;
+        }
+        __syncthreads();   // every thread has read its backward carry of pass B
+        sF[slot] = f;
+        sG[slot] = G;
+        __syncthreads();
+        if (leader) carry_scan(sF, sG, K, lpw, (int)threadIdx.x, false);
+        __syncthreads();
+        const C carry = sF[slot];
+        C bw, GB;
+        seg_middle<C, M, false>(v, r, cf, carry, bw, GB);
+        if (!head) {
+            bw = 0;
+            GB = 1;
+        }
+        sF[slot] = bw;
+        sG[slot] = GB;
+        __syncthreads();
+        if (leader) carry_scan(sF, sG, K, lpw, (int)threadIdx.x, true, ini[lpw + threadIdx.x]);
+        __syncthreads();
+        T* op = out + line0 + (int64_t)seg * M * st;
+        asm volatile("" : "+v"(op));
+        seg_last_store<T, C, M>(v, r, cf, sF[slot], op, st, head && valid ? M : 0);
+    });
 }
 
 // ------------------------------------------------------- kind 2 (x, LDS tile)
@@ -678,6 +861,14 @@ static int xpipe_depth(int need) { return need <= 2 ? 2 : (need <= 4 ? 4 : (need
 
 static int compute_size(int dtype) { return dtype == DT_F32_FAST ? 4 : 8; }
 
+// LDS of a kind-5 block: two carry arrays of K*lpw and two per-line carries
+// (compute type), the coefficient rows (ctab bytes) and the head's copy,
+// K0*M rows of lpw values (storage type)
+size_t halves_lds(int K, int lpw, int K0, int M, int es, int cs, size_t ctab)
+{
+    return (size_t)(2 * K * lpw + 2 * lpw) * cs + ctab + (size_t)K0 * M * lpw * es;
+}
+
 std::string check_plan(const SweepPlan& p, const AxisGeom& g, int dtype)
 {
     const int es = (int)dtype_size(dtype), cs = compute_size(dtype);
@@ -690,6 +881,17 @@ std::string check_plan(const SweepPlan& p, const AxisGeom& g, int dtype)
         const int64_t K = (int64_t)p.w * 64 / p.lpw;
         if (K * p.m < g.n) return "too few segments for the line length";
         if (4 * (int64_t)scan_slots((int)K, p.lpw, p.w * 64, false) * cs > max_lds()) return "LDS too large";
+        return "";
+    }
+    if (p.kind == PLAN_SEG_HALVES) {
+        if (p.lpw != 16 && p.lpw != 32 && p.lpw != 64) return "lpw must be 16, 32 or 64";
+        if (p.w < 1 || p.w > 8) return "w must be in [1, 8]";
+        if (g.outer > 65535) return "too many outer blocks for the strided kernel";
+        const int64_t K = (int64_t)p.w * 64 / p.lpw;
+        if (K * p.m >= g.n) return "the line fits one part: use kind 1";
+        if (2 * K * p.m < g.n) return "too few segments for the line length";
+        const int64_t K0 = ceil_div(g.n, p.m) - K;
+        if (halves_lds((int)K, p.lpw, (int)K0, p.m, es, cs, 0) > (size_t)max_lds()) return "LDS too large";
         return "";
     }
     if (p.kind == PLAN_SEG_XROWS) {
@@ -838,6 +1040,24 @@ SweepPlan default_plan(int axis, const AxisGeom& g, int dtype)
         }
         return p;   // kind 0
     }
+    // Lines of 1025..2048: the kind-1 tile of such a line is a block of up
+    // to 1024 threads, alone on its CU, which issues no loads while it
+    // scans; kind 5 takes the line in two parts with 512 threads (16 lines,
+    // M = 32), two blocks per CU, where their LDS fits (coefficient rows
+    // for a head of up to two segments assumed; a longer head falls back
+    // at launch).  Measured: 2000^3 x 8 FP32 y 144 -> 127 ms, z 167 -> 130
+    // ms; 1500^3 x 8 FP64 y 78.4 -> 77.3 ms, z 110.5 -> 95.1 ms.
+    if (g.n > 1024 && g.n <= 2048) {
+        SweepPlan c;
+        c.kind = PLAN_SEG_HALVES;
+        c.m = 32;
+        c.lpw = 16;
+        c.w = 8;
+        const int K = 32, K0 = (int)ceil_div(g.n, 32) - K;
+        const size_t ctab = (size_t)g.S * 4 * 33 * cs;
+        if (check_plan(c, g, dtype).empty() && halves_lds(K, 16, K0, 32, es, cs, ctab) <= (size_t)max_lds() / 2)
+            return c;
+    }
     // FP32 y lines on long axes: 32-line tiles (a full 128-byte line per
     // row) measured 2-3% faster than 16-line tiles on 1000^3 x 4; FP32 z
     // with FP64 arithmetic and FP64 lines keep 16-line tiles (z was 15%
@@ -928,6 +1148,35 @@ static hipError_t launch_seg(const SweepPlan& p, const AxisGeom& g, const T* in,
                              const C* invd, const C* r, const C* comp, int compH, hipStream_t st,
                              const T* xf, double* part)
 {
+    if (p.kind == PLAN_SEG_HALVES) {
+        // Runs as the kind-1 plan of twice the segments (one 1024-thread
+        // block per CU) where this kernel does not apply: the transposed
+        // sweeps, a grid without compressed coefficient rows, or LDS beyond
+        // half the CU's, which would leave no room for a second block.
+        const int threads = p.w * 64;
+        const int K = threads / p.lpw;
+        const int K0 = (int)(ceil_div(g.n, M) - K);
+        const int nh = compH >= 0 ? (compH + M - 1) / M : 0;
+        const bool comp_ok = comp && compH >= 0 && (g.n - 1) / M >= nh;
+        const size_t ctab = (size_t)g.S * (nh + 2) * (M + 1) * sizeof(C);   // no zero row
+        const size_t lds = halves_lds(K, p.lpw, K0, M, (int)sizeof(T), (int)sizeof(C), ctab);
+        if (TR || RED || !comp_ok || lds > (size_t)max_lds() / 2) {
+            SweepPlan q = p;
+            q.kind = PLAN_SEG_STRIDED;
+            q.w = 2 * p.w;
+            return launch_seg<T, C, TR, M, RED>(q, g, in, out, invd, r, comp, compH, st, xf, part);
+        }
+        if constexpr (!TR && !RED) {
+            dim3 grid((unsigned)ceil_div(g.inner, p.lpw), (unsigned)g.outer);
+            if (g.axis == 2)
+                hipLaunchKernelGGL((k_sweep_seg_halves<T, C, M, 2>), grid, dim3(threads), lds, st, in, out, g, r,
+                                   p.lpw, K0, comp, compH);
+            else
+                hipLaunchKernelGGL((k_sweep_seg_halves<T, C, M, 1>), grid, dim3(threads), lds, st, in, out, g, r,
+                                   p.lpw, K0, comp, compH);
+        }
+        return hipGetLastError();
+    }
     if (p.kind == PLAN_SEG_STRIDED || p.kind == PLAN_SEG_XROWS) {
         const bool xrows = p.kind == PLAN_SEG_XROWS;
         AxisGeom gg = g;

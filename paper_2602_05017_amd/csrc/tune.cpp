@@ -4,7 +4,8 @@
 // its fastest plan.  The candidates span the kernels of every plan kind:
 // LDS row tiles (plain and pipelined) and row lines for x, strided tiles of
 // 16, 32 or 64 lines for y and z, each with 8, 16 or 32 elements per
-// thread and as few segments as cover the line.
+// thread and as few segments as cover the line, and for y and z lines too
+// long for one 512-thread block the two-part tiles.
 #include <algorithm>
 #include <string>
 #include <vector>
@@ -54,6 +55,12 @@ std::vector<bfvm::SweepPlan> candidates(int axis, const bfvm::AxisGeom& g)
                 const int spw = 64 / lpw;
                 const int64_t K = cdiv(cdiv(g.n, M), spw) * spw;
                 if (K * lpw / 64 <= 16) add(bfvm::PLAN_SEG_STRIDED, M, K * lpw / 64, lpw);
+            }
+        // lines in two parts, 512-thread blocks
+        for (int M : {16, 32})
+            for (int lpw : {16, 32}) {
+                const int64_t K = 512 / lpw;
+                if (K * M < g.n && 2 * K * M >= g.n) add(bfvm::PLAN_SEG_HALVES, M, 8, lpw);
             }
     }
     return out;
