@@ -933,7 +933,6 @@ int bfvm_set_plan(bfvm_grid g, int32_t axis, int32_t kind, int32_t m, int32_t w,
     p.lpw = lpw;
     if ((kind == PLAN_SEG_XTILE || kind == PLAN_SEG_XROWS) && axis != 0)
         return fail(BFVM_EINVAL, "plan kinds 2 and 3 only run the x axis");
-    if (kind == PLAN_SEG_HALVES && axis == 0) return fail(BFVM_EINVAL, "plan kind 5 only runs the y and z axes");
     const std::string why = check_plan(p, axis_geom(axis, g->nx, g->ny, g->nz, g->S), g->dtype);
     if (!why.empty()) return fail(BFVM_EINVAL, "plan does not fit: " + why);
     g->plan[axis] = p;

@@ -352,7 +352,9 @@ __device__ __forceinline__ void seg_last_store(const C (&v)[M], C r, const Coef&
     }
 }
 
-template <typename T, typename C, int M, int AX>
+// XROWS: the x axis, every (row, substrate) one line whose elements lie S
+// apart inside the row's n*S run (as in kind 3); AX only names the axis.
+template <typename T, typename C, int M, bool XROWS, int AX>
 __global__ __launch_bounds__(512, 4) void k_sweep_seg_halves(const T* in, T* out, AxisGeom g,
                                                           const C* __restrict__ rr, int lpw, int K0,
                                                           const C* __restrict__ comp, int H)
@@ -382,7 +384,8 @@ __global__ __launch_bounds__(512, 4) void k_sweep_seg_halves(const T* in, T* out
     const int S = g.S;
     const int s = (int)((g.p0 + pa) % S);
     const int64_t st = g.stride;
-    const int64_t line0 = (g.o0 + (int64_t)by) * g.outer_stride + g.p0 + pa;
+    const int64_t line0 = XROWS ? ((g.p0 + pa) / S) * (g.n * S) + (pa % S)
+                                : (g.o0 + (int64_t)by) * g.outer_stride + g.p0 + pa;
     const bool head = seg < K0;
     const C r = rr[s];
     build_comp_rows<C, M>(tab, comp, H, n, S, cr);
@@ -886,7 +889,8 @@ std::string check_plan(const SweepPlan& p, const AxisGeom& g, int dtype)
     if (p.kind == PLAN_SEG_HALVES) {
         if (p.lpw != 16 && p.lpw != 32 && p.lpw != 64) return "lpw must be 16, 32 or 64";
         if (p.w < 1 || p.w > 8) return "w must be in [1, 8]";
-        if (g.outer > 65535) return "too many outer blocks for the strided kernel";
+        if (g.axis == 0 && ceil_div(g.outer * g.S, p.lpw) >= (1ll << 31)) return "too many lines";
+        if (g.axis != 0 && g.outer > 65535) return "too many outer blocks for the strided kernel";
         const int64_t K = (int64_t)p.w * 64 / p.lpw;
         if (K * p.m >= g.n) return "the line fits one part: use kind 1";
         if (2 * K * p.m < g.n) return "too few segments for the line length";
@@ -998,6 +1002,22 @@ SweepPlan default_plan(int axis, const AxisGeom& g, int dtype)
             c.lpw = 1;
             c.w = (int)ceil_div(per_row, 64);
             if (check_plan(c, g, dtype).empty()) return c;
+        }
+        // FP32 rows of 1025..2048 voxels: every (row, substrate) as a line
+        // taken in two parts (kind 5), two 512-thread blocks per CU where
+        // their LDS fits, as for y and z below.  Measured: 2000^3 x 8 FP32 x
+        // 157.2 -> 137.5 ms; FP64 rows gain nothing (1500^3 x 8: 76.4 ms as
+        // kind 3, 76.7 ms as kind 5) and keep kind 3.
+        if (es == 4 && g.n > 1024 && g.n <= 2048) {
+            SweepPlan c;
+            c.kind = PLAN_SEG_HALVES;
+            c.m = 32;
+            c.lpw = 16;
+            c.w = 8;
+            const int K = 32, K0 = (int)ceil_div(g.n, 32) - K;
+            const size_t ctab = (size_t)g.S * 4 * 33 * cs;
+            if (check_plan(c, g, dtype).empty() && halves_lds(K, 16, K0, 32, es, cs, ctab) <= (size_t)max_lds() / 2)
+                return c;
         }
         // preferred: every (row, substrate) as a line of the strided kernel;
         // 32 lines per tile where 16 segments or fewer cover a line (measured
@@ -1162,18 +1182,26 @@ static hipError_t launch_seg(const SweepPlan& p, const AxisGeom& g, const T* in,
         const size_t lds = halves_lds(K, p.lpw, K0, M, (int)sizeof(T), (int)sizeof(C), ctab);
         if (TR || RED || !comp_ok || lds > (size_t)max_lds() / 2) {
             SweepPlan q = p;
-            q.kind = PLAN_SEG_STRIDED;
+            q.kind = g.axis == 0 ? PLAN_SEG_XROWS : PLAN_SEG_STRIDED;
             q.w = 2 * p.w;
             return launch_seg<T, C, TR, M, RED>(q, g, in, out, invd, r, comp, compH, st, xf, part);
         }
         if constexpr (!TR && !RED) {
-            dim3 grid((unsigned)ceil_div(g.inner, p.lpw), (unsigned)g.outer);
-            if (g.axis == 2)
-                hipLaunchKernelGGL((k_sweep_seg_halves<T, C, M, 2>), grid, dim3(threads), lds, st, in, out, g, r,
-                                   p.lpw, K0, comp, compH);
-            else
-                hipLaunchKernelGGL((k_sweep_seg_halves<T, C, M, 1>), grid, dim3(threads), lds, st, in, out, g, r,
-                                   p.lpw, K0, comp, compH);
+            if (g.axis == 0) {   // every (row, substrate) of the x axis is one line
+                AxisGeom gg = g;
+                gg.inner = g.outer * g.S;
+                gg.outer = 1;
+                hipLaunchKernelGGL((k_sweep_seg_halves<T, C, M, true, 0>), dim3((unsigned)ceil_div(gg.inner, p.lpw)),
+                                   dim3(threads), lds, st, in, out, gg, r, p.lpw, K0, comp, compH);
+            } else {
+                dim3 grid((unsigned)ceil_div(g.inner, p.lpw), (unsigned)g.outer);
+                if (g.axis == 2)
+                    hipLaunchKernelGGL((k_sweep_seg_halves<T, C, M, false, 2>), grid, dim3(threads), lds, st, in,
+                                       out, g, r, p.lpw, K0, comp, compH);
+                else
+                    hipLaunchKernelGGL((k_sweep_seg_halves<T, C, M, false, 1>), grid, dim3(threads), lds, st, in,
+                                       out, g, r, p.lpw, K0, comp, compH);
+            }
         }
         return hipGetLastError();
     }

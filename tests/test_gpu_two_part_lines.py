@@ -1,11 +1,12 @@
-"""Plan kind 5: y and z lines longer than one block's K = 64 w / lpw
-segments of M cover (K*M < n <= 2*K*M), taken in two parts by one block,
-the first part kept in LDS between its passes.
+"""Plan kind 5: lines longer than one block's K = 64 w / lpw segments of M
+cover (K*M < n <= 2*K*M), taken in two parts by one block, the first part
+kept in LDS between its passes: y and z lines in the kind-1 layout, x with
+every (row, substrate) one line as in kind 3.
 
 Against the FP64 oracle at each storage form's bar, on ragged line lengths
 and tiles (heads of one segment up to K segments, tails up to K*M), with
-sources and Dirichlet entries; and against the kind-1 plan of twice the
-segments, whose carry scans the two-part form repeats step by step (idle
+sources and Dirichlet entries; and against the kind-1 (kind-3 on x) plan of
+twice the segments, whose carry scans the two-part form repeats step by step (idle
 segments pass every carry through unchanged), within 16 units of rounding
 of the storage form: the two kernels compute the same expressions, but the
 compiler fuses multiplies and adds differently in them (measured: 1-ulp
@@ -36,7 +37,7 @@ CASES = [
 
 def _shape(axis, n):
     other = (7, 5) if n <= 512 else (3, 2)
-    return (other[0], n, other[1]) if axis == 1 else (other[0], other[1], n)
+    return {0: (n, other[0], other[1]), 1: (other[0], n, other[1]), 2: (other[0], other[1], n)}[axis]
 
 
 def _run(p, dtype, axis, plan, nsteps):
@@ -51,7 +52,7 @@ def _run(p, dtype, axis, plan, nsteps):
 
 
 @pytest.mark.parametrize("m,lpw,w,n", CASES)
-@pytest.mark.parametrize("axis", [1, 2])
+@pytest.mark.parametrize("axis", [0, 1, 2])
 @pytest.mark.parametrize("dtype", ["f64", "f32", "f32fast"])
 def test_two_part_lines_match_oracle_and_the_one_part_plan(m, lpw, w, n, axis, dtype):
     import torch
@@ -60,7 +61,7 @@ def test_two_part_lines_match_oracle_and_the_one_part_plan(m, lpw, w, n, axis, d
     p = small_problem(shape, S, seed=700 + n + axis, nsrc=60, ndir=12, nsteps=2)
     p.dtype = dtype
     two = _run(p, dtype, axis, (5, m, w, lpw), 2)
-    one = _run(p, dtype, axis, (1, m, 2 * w, lpw), 2)
+    one = _run(p, dtype, axis, (3 if axis == 0 else 1, m, 2 * w, lpw), 2)
     a = two.double().cpu().numpy()
     d = rel_err(a, one.double().cpu().numpy())[0]
     assert d <= 16 * EPS[dtype], (m, lpw, w, n, axis, dtype, d)
@@ -72,7 +73,7 @@ def test_two_part_plans_are_checked():
     import paper_2602_05017_amd as bf
     p = small_problem((40, 100, 30), 2, seed=731, nsteps=1)
     g = make_grid(p)
-    for axis, plan in ((0, (5, 8, 2, 16)),      # x is not taken
+    for axis, plan in ((0, (5, 8, 2, 16)),      # K*M = 64 >= 40 on x: one part covers the line
                        (1, (5, 8, 4, 16)),      # K*M = 128 >= 100: one part covers the line
                        (1, (5, 4, 2, 16)),      # 2*K*M = 64 < 100
                        (1, (5, 8, 16, 16)),     # more than 512 threads
