@@ -13,7 +13,11 @@ agents, simulation, final save, each stage timed (fields saved as .npy).
 
 --workload liver12 / liver16: the larger Table 1 cubes on one GPU, 1500^3 x 8
 in FP64 (216 GB) and 2000^3 x 8 in FP32 (256 GB), fields written on the device
-(5 timed steps by default).  --workload liver4: Table 1's one-node case, 500^3 x 2
+(5 timed steps by default); their long lines run in two parts per block (plan
+kind 5), or with --one-part-plans as one-part plans (kinds 1 and 3, as few
+segments as cover the line: blocks of 768-1024 threads, one per CU) for
+comparison.
+--workload liver4: Table 1's one-node case, 500^3 x 2
 in FP64 (50 timed steps), with the oracle on a bounded sample beside it.
 
 --workload adjoint: the differentiation workload, 128^3 x 2 substrates, 50
@@ -83,6 +87,8 @@ def parse():
                     help="only copy a 4 GiB buffer twice (reference for FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--placement-candidates", type=int, default=4,
                     help="allocations the library times to place each field (1: a plain allocation)")
+    ap.add_argument("--one-part-plans", action="store_true",
+                    help="liver12/liver16: run kind-5 axes as the one-part plan of twice the segments")
     return ap.parse_args()
 
 
@@ -541,6 +547,14 @@ def run_large(args):
     e = 8 if p.dtype == "f64" else 4
     log(f"workload {p.name}: {upd:.4g} voxel-substrates, field {upd * e / 1e9:.0f} GB, sources {len(p.src)}")
     g = make_grid(p, p.dtype)
+    if args.one_part_plans:
+        # as few segments as cover the line, whole waves of 64 / lpw segments
+        for a in range(3):
+            kind, m, w, lpw = g.get_plan(a)
+            if kind == 5:
+                spw = 64 // lpw
+                K = -(-(-(-p.shape[2 - a] // m)) // spw) * spw
+                g.set_plan(a, 3 if a == 0 else 1, m, K * lpw // 64, lpw)
     # the library places the field among as many candidate allocations as
     # fit beside it (one for the 216 GB and 256 GB cubes)
     u, cand_ms = g.alloc_field(args.placement_candidates)

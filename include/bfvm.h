@@ -245,9 +245,9 @@ int bfvm_get_schedule(bfvm_grid g, int32_t* schedule, int64_t* slab_width);
  * 5 the kind-1 layout (y/z) or the kind-3 layout (x) with each line taken
  * in two parts by one block of at most 512 threads, the first part kept in
  * LDS between its passes (lines of K*m < n <= 2*K*m, K = 64*w/lpw; runs as
- * the kind-1 / kind-3 plan of twice the segments for the transposed sweeps,
- * or where the coefficient rows and the LDS copy would take more than half
- * of the CU's LDS).
+ * the kind-1 / kind-3 plan with as few segments as cover the line for the
+ * transposed sweeps, or where the coefficient rows and the LDS copy would
+ * take more than half of the CU's LDS).
  * m: elements per thread; w: waves per workgroup; lpw: lines per wave
  * (strided kernels) or rows per workgroup (LDS kernels).  bfvm_set_plan
  * validates the plan against the grid and the device's LDS per workgroup

@@ -1169,8 +1169,9 @@ static hipError_t launch_seg(const SweepPlan& p, const AxisGeom& g, const T* in,
                              const T* xf, double* part)
 {
     if (p.kind == PLAN_SEG_HALVES) {
-        // Runs as the kind-1 plan of twice the segments (one 1024-thread
-        // block per CU) where this kernel does not apply: the transposed
+        // Runs as the kind-1 (x: kind-3) plan with as few segments as cover
+        // the line (at most twice this plan's: one block of up to 1024
+        // threads per CU) where this kernel does not apply: the transposed
         // sweeps, a grid without compressed coefficient rows, or LDS beyond
         // half the CU's, which would leave no room for a second block.
         const int threads = p.w * 64;
@@ -1183,7 +1184,8 @@ static hipError_t launch_seg(const SweepPlan& p, const AxisGeom& g, const T* in,
         if (TR || RED || !comp_ok || lds > (size_t)max_lds() / 2) {
             SweepPlan q = p;
             q.kind = g.axis == 0 ? PLAN_SEG_XROWS : PLAN_SEG_STRIDED;
-            q.w = 2 * p.w;
+            const int spw = 64 / p.lpw;
+            q.w = (int)(ceil_div(ceil_div(g.n, M), spw) * spw * p.lpw / 64);
             return launch_seg<T, C, TR, M, RED>(q, g, in, out, invd, r, comp, compH, st, xf, part);
         }
         if constexpr (!TR && !RED) {

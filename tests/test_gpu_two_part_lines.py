@@ -88,8 +88,9 @@ def test_two_part_plans_are_checked():
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_reverse_step_with_two_part_plans(dtype):
-    # the transposed sweeps of a kind-5 axis run as the kind-1 plan of twice
-    # the segments: the reverse step still matches the oracle's adjoint
+    # the transposed sweeps of a kind-5 axis run as a kind-1 plan (as few
+    # segments as cover the line): the reverse step still matches the
+    # oracle's adjoint
     import torch
     p = small_problem((9, 100, 70), 2, seed=741, nsrc=40, ndir=10, nsteps=1)
     p.dtype = dtype
