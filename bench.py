@@ -404,10 +404,13 @@ def run_batch(args):
 
 
 # algorithmic bytes per element of one reverse step without sources and
-# Dirichlet entries, in units of the element size: three recomputed sweeps
-# (6, the first reading the state itself) and three transposed sweeps that
-# also read the recomputed output to form the parameter sums (9)
-ADJOINT_ELEMS_MOVED = 15
+# Dirichlet entries, z lines of at most 512 voxels, in units of the element
+# size: the recomputed x and y sweeps (4, the first reading the state
+# itself), the fused z pass (3: it reads the y output and the gradient and
+# writes the gradient; the z output lives in registers) and the x and y
+# transposed sweeps that also read the recomputed output for the parameter
+# sums (6)
+ADJOINT_ELEMS_MOVED = 13
 
 
 def run_adjoint(args):

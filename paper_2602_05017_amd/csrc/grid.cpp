@@ -434,6 +434,12 @@ int adjoint_enqueue(bfvm_grid g, const void* field_in, void* grad, void* const w
     const int S = g->S;
     hipStream_t st = g->stream;
     int rc;
+    const bool f32c = g->dtype == BFVM_F32_FAST;
+    const AxisGeom zgeo = axis_geom(2, g->nx, g->ny, g->nz, S);
+    const void* zcomp = f32c ? (const void*)g->comp32[2] : (const void*)g->comp64[2];
+    // The z recomputation and the z transposed sweep run as one kernel where
+    // it applies: the z output is formed and consumed in registers.
+    const bool fuse_z = adj_z_fusable(g->dtype, zgeo, zcomp, g->comp_H[2]);
     // forward recomputation: work[a] = output of sweep a (before the following
     // Dirichlet overwrite).  Without Dirichlet entries sweep a reads work[a-1]
     // directly; with them it runs on an overwritten copy, so that work[a-1]
@@ -448,7 +454,18 @@ int adjoint_enqueue(bfvm_grid g, const void* field_in, void* grad, void* const w
         if ((rc = run_dirichlet(g, work[0]))) return rc;
         if ((rc = run_sweep(g, 0, work[0], work[0], false))) return rc;
     }
+    // the fused z pass reads the y output with the Dirichlet values applied:
+    // work[1] itself, or an overwritten copy in work[2]
+    const void* zin = work[1];
     for (int a = 1; a < 3; ++a) {
+        if (a == 2 && fuse_z) {
+            if (g->ndir > 0) {
+                HIP_TRY(hipMemcpyAsync(work[2], work[1], bytes, hipMemcpyDeviceToDevice, st), "copy");
+                if ((rc = run_dirichlet(g, work[2]))) return rc;
+                zin = work[2];
+            }
+            break;
+        }
         if (g->ndir > 0) {
             HIP_TRY(hipMemcpyAsync(work[a], work[a - 1], bytes, hipMemcpyDeviceToDevice, st), "copy");
             if ((rc = run_dirichlet(g, work[a]))) return rc;
@@ -471,6 +488,16 @@ int adjoint_enqueue(bfvm_grid g, const void* field_in, void* grad, void* const w
     for (int a = 2; a >= 0; --a) {
         hipError_t e = launch_mask(g->dtype, grad, g->dir_elem, g->ndir, st);
         if (e != hipSuccess) return hip_fail(e, "mask kernel");
+        if (a == 2 && fuse_z) {
+            const void* invd = f32c ? (const void*)g->invd32[2] : (const void*)g->invd64[2];
+            const void* r = f32c ? (const void*)g->r32[2] : (const void*)g->r64[2];
+            hipEvent_t t0;
+            time_begin(g, 4, &t0);
+            e = launch_adj_z_fused(g->dtype, zgeo, zin, grad, invd, r, zcomp, g->comp_H[2], part[2], st);
+            time_end(g, 4, t0, zgeo.n * zgeo.inner * zgeo.outer);
+            if (e != hipSuccess) return hip_fail(e, "fused z reverse kernel");
+            continue;
+        }
         AdjSums red;
         red.x = work[a];
         red.part = part[a];

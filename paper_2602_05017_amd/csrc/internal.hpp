@@ -107,6 +107,15 @@ hipError_t launch_dirichlet(int dtype, void* u, const int64_t* elem, const doubl
                             int64_t cnt, hipStream_t stream);
 hipError_t launch_mask(int dtype, void* g, const int64_t* elem, int64_t cnt, hipStream_t stream);
 
+// The reverse step's z axis in one pass (sweep.hip): the forward z sweep of
+// zin recomputed in registers, the transposed z sweep of grad in place and
+// the per-line parameter sums part[2 L] (as the RED transposed sweep writes
+// them).  adj_z_fusable: whether this geometry takes it (z lines of up to
+// 512 voxels, the coefficient table or compressed rows in LDS).
+bool adj_z_fusable(int dtype, const AxisGeom& g, const void* comp, int compH);
+hipError_t launch_adj_z_fused(int dtype, const AxisGeom& g, const void* zin, void* grad, const void* invd,
+                              const void* r, const void* comp, int compH, double* part, hipStream_t stream);
+
 // Second stage of the per-line sums: out[(a*S + s)*2 + {0,1}] = the sum over
 // the lines L = s (mod S) of axis a (part[a], nlines[a] lines), in line order.
 hipError_t launch_adjoint_line_final(double* const part[3], const int64_t nlines[3], int S, double* out,

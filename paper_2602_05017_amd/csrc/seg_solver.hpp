@@ -22,19 +22,20 @@ namespace bfvm {
 
 // init: the carry entering the first segment in scan order; last (if not
 // null): where the carry leaving the last segment is written, at last[line].
-template <typename C>
+// UNR: segments whose LDS terms are loaded ahead of their multiply-adds.
+template <typename C, int UNR = 8>
 __device__ __forceinline__ void carry_scan(C* val, const C* prod, int K, int nl, int line, bool reverse,
                                            C init = 0, C* last = nullptr)
 {
     C c = init;
     if (!reverse) {
         int j = 0;
-        for (; j + 8 <= K; j += 8) {
-            C f[8], g[8];
+        for (; j + UNR <= K; j += UNR) {
+            C f[UNR], g[UNR];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) { f[u] = val[(j + u) * nl + line]; g[u] = prod[(j + u) * nl + line]; }
+            for (int u = 0; u < UNR; ++u) { f[u] = val[(j + u) * nl + line]; g[u] = prod[(j + u) * nl + line]; }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) { val[(j + u) * nl + line] = c; c = f[u] + g[u] * c; }
+            for (int u = 0; u < UNR; ++u) { val[(j + u) * nl + line] = c; c = f[u] + g[u] * c; }
         }
         for (; j < K; ++j) {
             const C f = val[j * nl + line], g = prod[j * nl + line];
@@ -43,12 +44,12 @@ __device__ __forceinline__ void carry_scan(C* val, const C* prod, int K, int nl,
         }
     } else {
         int j = K - 1;
-        for (; j - 8 >= -1; j -= 8) {
-            C f[8], g[8];
+        for (; j - UNR >= -1; j -= UNR) {
+            C f[UNR], g[UNR];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) { f[u] = val[(j - u) * nl + line]; g[u] = prod[(j - u) * nl + line]; }
+            for (int u = 0; u < UNR; ++u) { f[u] = val[(j - u) * nl + line]; g[u] = prod[(j - u) * nl + line]; }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) { val[(j - u) * nl + line] = c; c = f[u] + g[u] * c; }
+            for (int u = 0; u < UNR; ++u) { val[(j - u) * nl + line] = c; c = f[u] + g[u] * c; }
         }
         for (; j >= 0; --j) {
             const C f = val[j * nl + line], g = prod[j * nl + line];
@@ -262,7 +263,9 @@ __device__ __forceinline__ void seg_last(C (&v)[M], C r, const Coef& coef, C X)
 // arrays of scan_slots(K, nl, blockDim.x, PAR) carry terms each.  Every
 // thread of the block calls this (it holds barriers and shuffles); writer =
 // the thread owns a (segment, line) slot.
-template <typename C, int M, bool TR, bool PAR, typename Coef>
+// UNR: see carry_scan (fewer registers for the leader scan where a kernel
+// holds more than one segment's values)
+template <typename C, int M, bool TR, bool PAR, typename Coef, int UNR = 8>
 __device__ __forceinline__ void solve_segment(C (&v)[M], int seg, int K, int line, int nl, C r,
                                               const Coef& coef, C* sc, bool writer)
 {
@@ -281,7 +284,7 @@ __device__ __forceinline__ void solve_segment(C (&v)[M], int seg, int K, int lin
     }
     __syncthreads();
     if (KP) carry_scan_par(sF, sG, K, KP, nl, false);
-    else if ((int)threadIdx.x < nl) carry_scan(sF, sG, K, nl, threadIdx.x, false);
+    else if ((int)threadIdx.x < nl) carry_scan<C, UNR>(sF, sG, K, nl, threadIdx.x, false);
     __syncthreads();
     const C carry = writer ? sF[slot] : (C)0;
     C bw, GB;
@@ -292,7 +295,7 @@ __device__ __forceinline__ void solve_segment(C (&v)[M], int seg, int K, int lin
     }
     __syncthreads();
     if (KP) carry_scan_par(sB, sH, K, KP, nl, true);
-    else if ((int)threadIdx.x < nl) carry_scan(sB, sH, K, nl, threadIdx.x, true);
+    else if ((int)threadIdx.x < nl) carry_scan<C, UNR>(sB, sH, K, nl, threadIdx.x, true);
     __syncthreads();
     const C X = writer ? sB[slot] : (C)0;
     seg_last<C, M>(v, r, coef, X);

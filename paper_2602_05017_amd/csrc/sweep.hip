@@ -311,6 +311,120 @@ __global__ __launch_bounds__(1024) void k_sweep_seg_strided(const T* in, T* out,
     }
 }
 
+// ------------------------------- reverse step: z recomputation + z transposed
+//
+// The z axis of the reverse step in one pass.  The reverse step needs the
+// forward z sweep's output x (before the step's last Dirichlet overwrite)
+// only for the parameter sums of the transposed z sweep, which runs first.
+// Here each block recomputes x for its tile in registers (the forward solve
+// of zin, the y sweep's output with the Dirichlet values applied), then
+// solves the transposed system on the gradient in place, and forms the
+// sums y.(L_N x) and y.x from the two register arrays: x is never written
+// to memory or read back, so the reverse step moves 13 element values per
+// voxel-substrate instead of 15.  x enters the sums rounded to the storage
+// type, the value the two-kernel form reads back from its workspace; the
+// x values next to a segment come from the neighbouring segments through
+// LDS.  Tiles as kind 1 (lanes over neighbouring lines, waves over
+// segments), with M values of x and M of y per thread; COEF 1 (LDS copy of
+// the table) or 2 (compressed rows).
+template <typename T, typename C, int M, int COEF, int UNR>
+__global__ __launch_bounds__(512, 4) void k_adj_z_fused(const T* zin, T* grad, AxisGeom g,
+                                                        const C* __restrict__ invd, const C* __restrict__ rr,
+                                                        int lpw, int SP, FastDiv divS, const C* __restrict__ comp,
+                                                        int H, double* __restrict__ part)
+{
+    uint32_t bx, by;
+    xcd_tile(bx, by);
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int K = blockDim.x / lpw;
+    C* sc = reinterpret_cast<C*>(smem);
+    C* tab = sc + 4 * scan_slots(K, lpw, (int)blockDim.x, false);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int line = lane % lpw;
+    const int seg = wave * (64 / lpw) + lane / lpw;
+    const int64_t p = (int64_t)bx * lpw + line;
+    const bool valid = p < g.inner;
+    const int64_t pa = valid ? p : g.inner - 1;   // clamped line for padding loads
+    const int S = g.S;
+    const int s = (int)((g.p0 + pa) % S);
+    const int64_t i0 = (int64_t)seg * M;
+    const int64_t last = g.n - 1 - i0;            // slots k > last are padding
+    const int cnt = !valid || last < 0 ? 0 : (last >= M ? M : (int)last + 1);
+    const int64_t st = g.stride;
+    const int64_t base = (g.o0 + (int64_t)by) * g.outer_stride + g.p0 + pa + i0 * st;
+    const C r = rr[s];
+    const C prev = (i0 > 0 && last >= 0) ? invd[(i0 - 1) * S + s] : (C)0;
+    C x[M], y[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) x[k] = (C)zin[base + (k <= last ? k : last) * st];
+    // the leader scans load UNR segments' terms ahead (not 8): the x values
+    // stay live through the second solve
+    auto solve_both = [&](const auto& coef) {
+        using Cf = std::decay_t<decltype(coef)>;
+        solve_segment<C, M, false, false, Cf, UNR>(x, seg, K, line, lpw, r, coef, sc, true);
+        // opaque pointer and bound: the gradient's addresses are formed here
+        // instead of being kept live through the first solve
+        const T* gp = grad + base;
+        int lastv = (int)(last < M ? last : M);
+        asm volatile("" : "+v"(gp), "+v"(lastv));
+#pragma unroll
+        for (int k = 0; k < M; ++k) y[k] = (C)gp[(k <= lastv ? k : lastv) * st];
+        solve_segment<C, M, true, false, Cf, UNR>(y, seg, K, line, lpw, r, coef, sc, true);
+    };
+    if constexpr (COEF == 1) {
+        stage_table<C, M>(tab, invd, (uint32_t)g.n, (uint32_t)(K * M), (uint32_t)S, (uint32_t)SP, divS);
+        __syncthreads();
+        solve_both(LdsCoef<C>{tab + s * SP + seg * (M + 1), prev});
+    } else {
+        const CompRows<M> cr(H, (int)g.n);
+        build_comp_rows<C, M>(tab, comp, H, (int)g.n, S, cr);
+        __syncthreads();
+        solve_both(LdsCoef<C>{tab + s * cr.SPr + cr.row(seg) * (M + 1), prev});
+    }
+    T* op = grad + base;
+    asm volatile("" : "+v"(op));
+    if (cnt == M) {
+#pragma unroll
+        for (int k = 0; k < M; ++k) op[k * st] = (T)y[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < M; ++k)
+            if (k < cnt) op[k * st] = (T)y[k];
+    }
+    // x at the segment's ends for the neighbouring segments (the carry
+    // arrays hold at least two doubles per slot)
+    const int slot = seg * lpw + line;
+    double* xfirst = reinterpret_cast<double*>(sc);
+    double* xlast = xfirst + K * lpw;
+    __syncthreads();   // the solves' last reads of the carry arrays are done
+    xfirst[slot] = (double)(T)x[0];
+    xlast[slot] = (double)(T)x[M - 1];
+    __syncthreads();
+    const bool left = i0 > 0 && last >= 0;
+    double xl = left ? xlast[slot - lpw] : 0.0;
+    double a0 = 0.0, a1 = 0.0;
+    if (cnt > 0) {
+        double xc = (double)(T)x[0];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const double xn = k + 1 < M ? (double)(T)x[k + 1] : (k + 1 <= last ? xfirst[slot + lpw] : 0.0);
+            double lx = 0.0;
+            if (k > 0 || left) lx += xc - xl;
+            if (k + 1 <= last) lx += xc - xn;
+            if (k <= last) {
+                a0 += (double)y[k] * lx;
+                a1 += (double)y[k] * xc;
+            }
+            xl = xc;
+            xc = xn;
+        }
+    }
+    const int64_t p_first = (int64_t)bx * lpw;
+    line_sums_store<C>(a0, a1, seg, K, line, lpw, sc, false, true, part, (int64_t)by * g.inner + p_first,
+                       (int)min((int64_t)lpw, g.inner - p_first));
+}
+
 // ------------------------------------------ kind 5 (y/z, lines in two parts)
 //
 // For lines longer than one block's K = blockDim/lpw segments of M cover
@@ -1320,6 +1434,84 @@ static hipError_t launch_dir(bool transposed, const SweepPlan& plan, const AxisG
     if (!transposed) return launch_typed<T, C, false, false>(plan, g, in, out, invd, r, comp, compH, st, red);
     if (red.part) return launch_typed<T, C, true, true>(plan, g, in, out, invd, r, comp, compH, st, red);
     return launch_typed<T, C, true, false>(plan, g, in, out, invd, r, comp, compH, st, red);
+}
+
+constexpr int kAdjZUnr = 1;
+
+// z lines of up to 512 voxels: M = 16 values of x and of y per thread, K =
+// the power of two >= n/16 segments (at least 8), 512/K lines per tile
+static int adj_z_fused_k(int64_t n)
+{
+    if (n < 1 || n > 512) return 0;
+    int K = 8;
+    while ((int64_t)K * 16 < n) K *= 2;
+    return K;
+}
+
+template <typename T, typename C>
+static hipError_t launch_adj_z_fused_t(const AxisGeom& g, const void* zin, void* grad, const void* invd,
+                                       const void* r, const void* comp, int compH, double* part, hipStream_t st)
+{
+    constexpr int M = 16;
+    const int K = adj_z_fused_k(g.n);
+    const int lpw = 512 / K;
+    const int threads = 512;
+    const size_t scan = 4 * (size_t)scan_slots(K, lpw, threads, false) * sizeof(C);
+    const int period = sizeof(C) == 8 ? 16 : 32;
+    const int spw = 64 / lpw;
+    const int KM1 = K * (M + 1);
+    const int SP = KM1 + (((spw - KM1) % period) + period) % period;
+    const size_t tab = (size_t)g.S * SP * sizeof(C);
+    const int64_t KMS = (int64_t)K * M * g.S;
+    const bool lds_tab = scan + tab <= (size_t)max_lds() && KMS < (1 << 24) && KMS * g.S <= (1ll << 40);
+    const int nh = compH >= 0 ? (compH + M - 1) / M : 0;
+    const bool comp_ok = comp && compH >= 0 && (g.n - 1) / M >= nh;
+    const size_t ctab = comp_ok ? (size_t)g.S * (nh + 3) * (M + 1) * sizeof(C) : 0;
+    const bool use_comp = ctab > 0 && scan + ctab <= (size_t)max_lds() && (!lds_tab || tab > (48u << 10));
+    const dim3 grid((unsigned)ceil_div(g.inner, lpw), (unsigned)g.outer);
+    const FastDiv dS((uint32_t)g.S);
+    const T* zi = static_cast<const T*>(zin);
+    T* gr = static_cast<T*>(grad);
+    const C* cf = static_cast<const C*>(invd);
+    const C* rr = static_cast<const C*>(r);
+    const C* cc = static_cast<const C*>(comp);
+    if (use_comp)
+        hipLaunchKernelGGL((k_adj_z_fused<T, C, M, 2, kAdjZUnr>), grid, dim3(threads), scan + ctab, st, zi, gr, g, cf, rr, lpw,
+                           SP, dS, cc, compH, part);
+    else if (lds_tab)
+        hipLaunchKernelGGL((k_adj_z_fused<T, C, M, 1, kAdjZUnr>), grid, dim3(threads), scan + tab, st, zi, gr, g, cf, rr, lpw,
+                           SP, dS, cc, compH, part);
+    else
+        return hipErrorNotSupported;
+    return hipGetLastError();
+}
+
+bool adj_z_fusable(int dtype, const AxisGeom& g, const void* comp, int compH)
+{
+    if (g.axis != 2 || g.p0 != 0 || g.o0 != 0 || g.outer > 65535 || !adj_z_fused_k(g.n)) return false;
+    const int K = adj_z_fused_k(g.n);
+    const int cs = compute_size(dtype);
+    const size_t scan = 4 * (size_t)scan_slots(K, 512 / K, 512, false) * cs;
+    const int64_t KMS = (int64_t)K * 16 * g.S;
+    const bool lds_tab = scan + (size_t)g.S * (K * 17 + 32) * cs <= (size_t)max_lds() && KMS < (1 << 24) &&
+                         KMS * g.S <= (1ll << 40);
+    const int nh = compH >= 0 ? (compH + 15) / 16 : 0;
+    const bool comp_ok = comp && compH >= 0 && (g.n - 1) / 16 >= nh &&
+                         scan + (size_t)g.S * (nh + 3) * 17 * cs <= (size_t)max_lds();
+    return lds_tab || comp_ok;
+}
+
+hipError_t launch_adj_z_fused(int dtype, const AxisGeom& g, const void* zin, void* grad, const void* invd,
+                              const void* r, const void* comp, int compH, double* part, hipStream_t st)
+{
+    if (g.inner * g.outer == 0) return hipSuccess;
+    if (!adj_z_fusable(dtype, g, comp, compH)) return hipErrorNotSupported;
+    switch (dtype) {
+        case DT_F64: return launch_adj_z_fused_t<double, double>(g, zin, grad, invd, r, comp, compH, part, st);
+        case DT_F32: return launch_adj_z_fused_t<float, double>(g, zin, grad, invd, r, comp, compH, part, st);
+        case DT_F32_FAST: return launch_adj_z_fused_t<float, float>(g, zin, grad, invd, r, comp, compH, part, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_sweep(int dtype, bool transposed, const SweepPlan& plan, const AxisGeom& g,

@@ -242,3 +242,38 @@ def test_backward_uses_its_own_forward_params_after_another_forward_on_the_grid(
     assert np.max(np.abs(D2.grad.numpy() - rgD2) / np.abs(rgD2)) <= 1e-11
     assert np.max(np.abs(L2.grad.numpy() - rgL2) / np.abs(rgL2)) <= 1e-11
     g.close()
+
+
+@pytest.mark.parametrize("nz", [64, 500, 512, 513, 600])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f32fast"])
+def test_reverse_step_z_pass_fused_and_two_kernel(nz, dtype):
+    # z lines of up to 512 voxels run the z recomputation and the z
+    # transposed sweep as one kernel (k_adj_z_fused: the z output formed and
+    # consumed in registers); longer lines run the two kernels with the
+    # workspace between them.  Both against the oracle's adjoint of the
+    # state and gradient the GPU holds: the gradient at the storage form's
+    # bar, dL/dD and dL/dlambda within their normwise bars; the kernel names
+    # the profiler records show which form ran
+    import torch
+    from torch.profiler import ProfilerActivity, profile
+    from gpu_helpers import oracle_adjoint, param_grad_bars
+    p = small_problem((5, 3, nz), 2, seed=810 + nz, nsrc=30, ndir=8)
+    p.dtype = dtype
+    rng = np.random.default_rng(nz)
+    gin = (rng.random(p.shape) - 0.5).astype(np.float64 if dtype == "f64" else np.float32)
+    g = make_grid(p, dtype)
+    u = upload(p, g)
+    gg = torch.from_numpy(gin.copy()).cuda()
+    torch.cuda.synchronize()
+    with profile(activities=[ProfilerActivity.CUDA]) as prof:
+        gD, gL = g.step_adjoint(u, gg)
+        torch.cuda.synchronize()
+    names = {e.name for e in prof.events()}
+    state = g.read_field(u)
+    g.close()
+    assert any("k_adj_z_fused" in n for n in names) == (nz <= 512), sorted(names)
+    rg, rD, rL = oracle_adjoint(p, state, gin)
+    barD, barL = param_grad_bars(p, state, gin)
+    e = rel_err(gg.double().cpu().numpy(), rg)[0]
+    assert e <= {"f64": 1e-12, "f32": 1e-5, "f32fast": 1e-5}[dtype], (nz, dtype, e)
+    assert np.all(np.abs(gD - rD) <= barD) and np.all(np.abs(gL - rL) <= barL), (nz, dtype)
