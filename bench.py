@@ -33,6 +33,13 @@ voxels as sources), autotuned, stepped together by one graph replay per step
 --workload ceiling: the device's streaming ceilings (write only, read only,
 in-place read+write, copy) on a 32 GB buffer.
 
+--workload xslab: one process's share of the distributed x sweep (Sec. 3.2)
+at the paper's 8-node split of the 1000^3 x 4 cube: a 125-voxel x-slab (4
+GB, FP64), its forward and backward shares over 16 blocks of lines (blocks
+= 2 x 8 processes, Eq. 5), against the same slab swept as a whole grid; and
+all 8 slabs of the cube chained on one GPU, one stream per slab with the
+block hand-offs as events, against the whole-line x sweep of the cube.
+
 Fields are placed by the library (bfvm_field_alloc): the sweeps' rate depends
 on where a field's allocation lands in device memory, so --placement-candidates
 allocations (default 4) are timed on one sweep set each and the fastest is
@@ -76,7 +83,7 @@ def parse():
                     help="timed steps (default 20; 100 for the batch workload)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="liver",
-                    choices=["liver", "cells", "gaussian", "batch", "adjoint", "liver4", "liver12", "liver16",
+                    choices=["liver", "cells", "gaussian", "batch", "adjoint", "liver4", "liver12", "liver16", "xslab",
                              "endtoend", "ceiling"])
     ap.add_argument("--adjoint-steps", type=int, default=5,
                     help="batch workload: timed reverse steps of the 32-domain subset")
@@ -721,6 +728,142 @@ def rmw_ceiling(u, reps: int = 3):
             "bytes": nbytes}
 
 
+def run_xslab(args):
+    """One x-slab's share of the distributed x sweep at the paper's 8-node
+    split of the tumour-scale cube (1000^3 x 4 FP64), and the 8 slabs chained
+    on one GPU.  The carries entering a slab are seeded values for the slab
+    measured alone (any finite values exercise the same work)."""
+    import torch
+    import workloads
+    import paper_2602_05017_amd as bf
+    reps = 5 if args.steps is None else args.steps
+    p = workloads.config(3, with_field=False)
+    P, NB = 8, 16
+    n, S = p.nx, p.S
+    xb = [n * r // P for r in range(P + 1)]
+    nl = p.ny * p.nz * S
+    lb = [nl * b // NB for b in range(NB + 1)]
+    g = bf.Grid(n, p.ny, p.nz, S, tuple(p.h), dtype="f64")
+    g.set_params(p.D, p.lam, p.dt)
+    # ---- one slab (a middle process), forward then backward over the blocks
+    x0, x1 = xb[P // 2], xb[P // 2 + 1]
+    m = x1 - x0
+    slab = torch.empty((p.nz, p.ny, m, S), dtype=torch.float64, device="cuda")
+    slab.uniform_(0.0, 1.0, generator=torch.Generator(device="cuda").manual_seed(p.seed))
+    cin = torch.empty(nl, dtype=torch.float64, device="cuda").uniform_(0.0, 1.0)
+    cout = torch.empty(nl, dtype=torch.float64, device="cuda")
+
+    def one_slab():
+        for b in range(NB):
+            g.xslab_forward(slab, x0, x1, lb[b], lb[b + 1], cin[lb[b]:], cout[lb[b]:])
+        for b in range(NB):
+            g.xslab_backward(slab, x0, x1, lb[b], lb[b + 1], cin[lb[b]:], cout[lb[b]:])
+
+    one_slab()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        one_slab()
+    e1.record()
+    torch.cuda.synchronize()
+    t_slab = e0.elapsed_time(e1) / reps
+    elems = m * nl
+    alg = 4 * 8 * elems                      # read + write in each direction
+    # the same slab swept as a grid of its own (whole lines of 125, 2 moves)
+    gs = bf.Grid(m, p.ny, p.nz, S, tuple(p.h), dtype="f64")
+    gs.set_params(p.D, p.lam, p.dt)
+    gs.sweep(slab, 0)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        gs.sweep(slab, 0)
+    e1.record()
+    torch.cuda.synchronize()
+    t_whole_slab = e0.elapsed_time(e1) / reps
+    gs.close()
+    del slab, cin, cout
+    torch.cuda.empty_cache()
+    log(f"x-slab {m}x{p.ny}x{p.nz}x{S}: forward + backward over {NB} blocks {t_slab:.3f} ms "
+        f"({alg / (t_slab * 1e-3) / 1e9:.0f} GB/s at 4 moves); as a grid of its own {t_whole_slab:.3f} ms")
+    # ---- the 8 slabs chained on one GPU: one stream per slab, events for the
+    # block hand-offs (forward slab r after slab r-1, backward after slab r+1)
+    u = torch.empty(p.shape, dtype=torch.float64, device="cuda")
+    g.fill_uniform(u, p.seed, 0)
+    slabs = [u[:, :, xb[r]:xb[r + 1], :].clone(memory_format=torch.contiguous_format) for r in range(P)]
+    fwd_c = [torch.empty(nl, dtype=torch.float64, device="cuda") for _ in range(P)]
+    bwd_c = [torch.empty(nl, dtype=torch.float64, device="cuda") for _ in range(P)]
+    streams = [torch.cuda.Stream() for _ in range(P)]
+    main = torch.cuda.current_stream()
+
+    def chained():
+        done_f = [[torch.cuda.Event() for _ in range(NB)] for _ in range(P)]
+        done_b = [[torch.cuda.Event() for _ in range(NB)] for _ in range(P)]
+        start = torch.cuda.Event()
+        start.record(main)
+        for r in range(P):
+            streams[r].wait_event(start)
+        for b in range(NB):
+            l0, l1 = lb[b], lb[b + 1]
+            for r in range(P):
+                with torch.cuda.stream(streams[r]):
+                    if r > 0:
+                        streams[r].wait_event(done_f[r - 1][b])
+                    g.xslab_forward(slabs[r], xb[r], xb[r + 1], l0, l1, fwd_c[r - 1][l0:] if r > 0 else None,
+                                    fwd_c[r][l0:])
+                    done_f[r][b].record(streams[r])
+        for b in range(NB):
+            l0, l1 = lb[b], lb[b + 1]
+            for r in reversed(range(P)):
+                with torch.cuda.stream(streams[r]):
+                    if r < P - 1:
+                        streams[r].wait_event(done_b[r + 1][b])
+                    else:
+                        streams[r].wait_event(done_f[r][b])
+                    g.xslab_backward(slabs[r], xb[r], xb[r + 1], l0, l1, bwd_c[r + 1][l0:] if r < P - 1 else None,
+                                     bwd_c[r][l0:])
+                    done_b[r][b].record(streams[r])
+        for r in range(P):
+            main.wait_stream(streams[r])
+
+    chained()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        chained()
+    torch.cuda.synchronize()
+    t_chain = (time.perf_counter() - t0) * 1e3 / reps
+    # the whole-line x sweep of the cube for comparison
+    g.sweep(u, 0)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        g.sweep(u, 0)
+    e1.record()
+    torch.cuda.synchronize()
+    t_whole = e0.elapsed_time(e1) / reps
+    g.close()
+    upd = p.V * S
+    log(f"8 slabs chained: {t_chain:.3f} ms per x sweep; whole-line x sweep {t_whole:.3f} ms")
+    line = {
+        "metric": "voxel-substrate updates/s of one x-slab's share of the distributed x sweep (FP64)",
+        "value": elems / (t_slab * 1e-3), "unit": "voxel-substrate updates/s", "n_gpus": 1, "steps": reps,
+        "warmup": 1, "ms_per_step": round(t_slab, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded uniform slab and carries)",
+        "config": {"workload": f"xslab-{m}x{p.ny}x{p.nz}x{S}-of-1000^3x4-f64", "processes": P, "blocks": NB,
+                   "slab": [x0, x1]},
+        "roofline": {"bound": "hbm", "achieved": round(alg / (t_slab * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(alg / (t_slab * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "kernel": "k_xslab (forward + backward over the blocks)",
+                     "algorithmic_bytes_per_step": alg},
+        "slab_as_a_grid_ms": round(t_whole_slab, 4),
+        "chained_8_slabs": {"ms_per_x_sweep": round(t_chain, 3), "updates_per_s": upd / (t_chain * 1e-3),
+                            "whole_line_x_sweep_ms": round(t_whole, 3), "streams": P, "blocks": NB},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def run_ceiling(args):
     """Streaming ceilings of the device on a buffer the size of the
     1000^3 x 4 FP64 field (32 GB), with torch's vectorised kernels: write
@@ -792,6 +935,9 @@ def main():
         return
     if args.workload == "ceiling":
         run_ceiling(args)
+        return
+    if args.workload == "xslab":
+        run_xslab(args)
         return
     if args.steps is None:
         args.steps = 20

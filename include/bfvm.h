@@ -121,6 +121,40 @@ int bfvm_step(bfvm_grid g, void* field, int64_t nsteps);
  * Errors: EINVAL, ESTATE, EDEVICE. */
 int bfvm_sweep(bfvm_grid g, void* field, int32_t axis);
 
+/* One x-slab's share of the x sweep in the distributed solver of Sec. 3.2
+ * (the domain split along x into slabs, one per process; the forward
+ * elimination runs slab after slab and hands each slab's last x-plane of
+ * eliminated values to the next; the backward substitution runs back and
+ * hands each slab's first x-plane of solution values to the previous; the
+ * lines are processed in blocks, k * processes of them by Eq. 5, so that
+ * the slabs overlap).  Chained forward over slabs 0..P-1 and backward over
+ * P-1..0 for every block of lines, the two calls give bfvm_sweep's x sweep
+ * up to rounding order.
+ *   g:      the grid of the WHOLE domain (global nx, ny, nz, S; params set):
+ *           its Thomas constants at global x positions are used;
+ *   slab:   device array of the slab, [nz][ny][x1 - x0][S] of the grid's
+ *           storage type (x fastest, then substrate innermost), updated in
+ *           place: the forward call replaces the field values by the
+ *           eliminated values d', the backward call d' by the solution;
+ *   x0, x1: the slab's x range, 0 <= x0 < x1 <= nx, x1 - x0 <= 2048;
+ *   l0, l1: the block of lines, 0 <= l0 < l1 <= ny * nz * S; line
+ *           L = (z * ny + y) * S + s;
+ *   carry_in:  device array of l1 - l0 values of the compute type (double;
+ *           float for BFVM_F32_FAST), entry L - l0 for line L: forward,
+ *           d' at x0 - 1 (NULL exactly when x0 == 0); backward, the
+ *           solution at x1 (NULL exactly when x1 == nx);
+ *   carry_out: device array of l1 - l0 compute-type values: forward, d' at
+ *           x1 - 1; backward, the solution at x0.
+ * Asynchronous on the grid's stream; allocates nothing; the arrays are the
+ * caller's.  Each call reads and writes every slab element of its lines
+ * once.  Errors: EINVAL (ranges, NULL slab or carry_out, carry_in given or
+ * missing against the rule above, a slab longer than 2048 or whose
+ * constants do not fit the LDS), ESTATE (no params), EDEVICE. */
+int bfvm_xslab_forward(bfvm_grid g, void* slab, int64_t x0, int64_t x1, int64_t l0, int64_t l1, const void* carry_in,
+                       void* carry_out);
+int bfvm_xslab_backward(bfvm_grid g, void* slab, int64_t x0, int64_t x1, int64_t l0, int64_t l1,
+                        const void* carry_in, void* carry_out);
+
 /* Reverse of one step (not in the paper; the transpose of the step above).
  * field_in: device field at the START of the forward step (not modified).
  * grad: device field, on entry dL/du after the step, on exit dL/du before it.

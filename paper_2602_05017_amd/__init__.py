@@ -29,7 +29,8 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ERANGE", -3: "ESTATE", -4: "EDEVICE", -5: 
 # every entry point declared in include/bfvm.h
 EXPORTS = [
     "bfvm_create", "bfvm_destroy", "bfvm_set_stream", "bfvm_set_params", "bfvm_set_sources",
-    "bfvm_set_dirichlet", "bfvm_step", "bfvm_sweep", "bfvm_step_adjoint", "bfvm_step_adjoint_noalloc",
+    "bfvm_set_dirichlet", "bfvm_step", "bfvm_sweep", "bfvm_xslab_forward", "bfvm_xslab_backward",
+    "bfvm_step_adjoint", "bfvm_step_adjoint_noalloc",
     "bfvm_read_field",
     "bfvm_save_npy", "bfvm_load_npy",
     "bfvm_fill_uniform", "bfvm_fill_gaussian", "bfvm_device_bytes",
@@ -78,6 +79,8 @@ def lib():
     L.bfvm_set_dirichlet.argtypes = [_vp, _i64, _i64p, _f64p, _u8p]
     L.bfvm_step.argtypes = [_vp, _vp, _i64]
     L.bfvm_sweep.argtypes = [_vp, _vp, _i32]
+    L.bfvm_xslab_forward.argtypes = [_vp, _vp, _i64, _i64, _i64, _i64, _vp, _vp]
+    L.bfvm_xslab_backward.argtypes = [_vp, _vp, _i64, _i64, _i64, _i64, _vp, _vp]
     L.bfvm_step_adjoint.argtypes = [_vp, _vp, _vp, _f64p, _f64p]
     L.bfvm_step_adjoint_noalloc.argtypes = [_vp, _vp, _vp, _f64p, _f64p]
     L.bfvm_read_field.argtypes = [_vp, _vp, _vp]
@@ -267,6 +270,33 @@ class Grid:
         self._sync_stream()
         _check(lib().bfvm_sweep(self._handle, p, int(axis)), "bfvm_sweep")
         return field
+
+    def _slab_args(self, slab, x0, x1, l0, l1, carry_in, carry_out):
+        import torch
+        for t in (slab, carry_out) + ((carry_in,) if carry_in is not None else ()):
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+                raise TypeError("slab and carries must be contiguous CUDA tensors")
+        if slab.dtype != self.torch_dtype or slab.numel() != (x1 - x0) * self.ny * self.nz * self.nsub:
+            raise ValueError("slab must hold nz*ny*(x1-x0)*nsub elements of the grid's dtype")
+        cdt = torch.float32 if self.dtype == "f32fast" else torch.float64
+        for t in (carry_out,) + ((carry_in,) if carry_in is not None else ()):
+            if t.dtype != cdt or t.numel() < l1 - l0:
+                raise ValueError(f"carries must hold l1 - l0 values of {cdt}")
+        cin = ctypes.c_void_p(carry_in.data_ptr()) if carry_in is not None else None
+        return (ctypes.c_void_p(slab.data_ptr()), int(x0), int(x1), int(l0), int(l1), cin,
+                ctypes.c_void_p(carry_out.data_ptr()))
+
+    def xslab_forward(self, slab, x0, x1, l0, l1, carry_in, carry_out):
+        """Forward share of the x sweep on slab [x0, x1), lines [l0, l1) (bfvm_xslab_forward)."""
+        a = self._slab_args(slab, x0, x1, l0, l1, carry_in, carry_out)
+        self._sync_stream()
+        _check(lib().bfvm_xslab_forward(self._handle, *a), "bfvm_xslab_forward")
+
+    def xslab_backward(self, slab, x0, x1, l0, l1, carry_in, carry_out):
+        """Backward share of the x sweep on slab [x0, x1), lines [l0, l1) (bfvm_xslab_backward)."""
+        a = self._slab_args(slab, x0, x1, l0, l1, carry_in, carry_out)
+        self._sync_stream()
+        _check(lib().bfvm_xslab_backward(self._handle, *a), "bfvm_xslab_backward")
 
     def step_adjoint(self, field_in, grad, grad_D=None, grad_lambda=None):
         """One reverse step; returns (grad_D, grad_lambda) accumulators (numpy)."""

@@ -16,7 +16,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libbfvm.so")
 
-SOURCES = ["sweep.hip", "sparse.hip", "batch.hip", "fill.hip", "noalloc.hip", "grid.cpp", "io.cpp", "tune.cpp"]
+SOURCES = ["sweep.hip", "slab.hip", "sparse.hip", "batch.hip", "fill.hip", "noalloc.hip", "grid.cpp", "io.cpp",
+           "tune.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,

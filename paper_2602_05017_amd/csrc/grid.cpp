@@ -805,6 +805,52 @@ int bfvm_sweep(bfvm_grid g, void* field, int32_t axis)
     return run_sweep(g, axis, field, field, false);
 }
 
+namespace {
+
+int xslab_run(bfvm_grid g, bool fwd, void* slab, int64_t x0, int64_t x1, int64_t l0, int64_t l1, const void* cin,
+              void* cout)
+{
+    if (int st = check_grid(g)) return st;
+    if (!g->have_params) return fail(BFVM_ESTATE, "set_params must come before the slab sweeps");
+    if (!slab || !cout) return fail(BFVM_EINVAL, "slab or carry_out is NULL");
+    if (x0 < 0 || x1 <= x0 || x1 > g->nx) return fail(BFVM_EINVAL, "need 0 <= x0 < x1 <= nx");
+    const int64_t nl = g->ny * g->nz * (int64_t)g->S;
+    if (l0 < 0 || l1 <= l0 || l1 > nl) return fail(BFVM_EINVAL, "need 0 <= l0 < l1 <= ny * nz * S");
+    const bool edge = fwd ? x0 == 0 : x1 == g->nx;
+    if (edge != (cin == nullptr))
+        return fail(BFVM_EINVAL, fwd ? "carry_in must be NULL exactly when x0 == 0"
+                                     : "carry_in must be NULL exactly when x1 == nx");
+    int M = 0, K = 0, lpw = 0;
+    if (!xslab_plan(x1 - x0, &M, &K, &lpw)) return fail(BFVM_EINVAL, "slab longer than 2048");
+    const bool f32c = g->dtype == BFVM_F32_FAST;
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, g->device) != hipSuccess)
+        return fail(BFVM_EDEVICE, "hipDeviceGetAttribute");
+    if (xslab_lds(M, K, lpw, g->S, f32c ? 4 : 8) > (size_t)lds_max)
+        return fail(BFVM_EINVAL, "the slab's constants do not fit the LDS");
+    const void* invd = f32c ? (const void*)g->invd32[0] : (const void*)g->invd64[0];
+    const void* r = f32c ? (const void*)g->r32[0] : (const void*)g->r64[0];
+    hipEvent_t a;
+    time_begin(g, 2, &a);
+    hipError_t e = launch_xslab(g->dtype, fwd, slab, x1 - x0, g->S, l0, l1 - l0, invd, r, x0, cin, cout, g->stream);
+    time_end(g, 2, a, (x1 - x0) * (l1 - l0));
+    return e == hipSuccess ? BFVM_OK : hip_fail(e, "slab sweep kernel");
+}
+
+}  // namespace
+
+int bfvm_xslab_forward(bfvm_grid g, void* slab, int64_t x0, int64_t x1, int64_t l0, int64_t l1, const void* carry_in,
+                       void* carry_out)
+{
+    return xslab_run(g, true, slab, x0, x1, l0, l1, carry_in, carry_out);
+}
+
+int bfvm_xslab_backward(bfvm_grid g, void* slab, int64_t x0, int64_t x1, int64_t l0, int64_t l1,
+                        const void* carry_in, void* carry_out)
+{
+    return xslab_run(g, false, slab, x0, x1, l0, l1, carry_in, carry_out);
+}
+
 int bfvm_step_adjoint(bfvm_grid g, const void* field_in, void* grad, double* grad_D, double* grad_lambda)
 {
     if (int st = check_grid(g)) return st;

@@ -116,6 +116,14 @@ bool adj_z_fusable(int dtype, const AxisGeom& g, const void* comp, int compH);
 hipError_t launch_adj_z_fused(int dtype, const AxisGeom& g, const void* zin, void* grad, const void* invd,
                               const void* r, const void* comp, int compH, double* part, hipStream_t stream);
 
+// One x-slab's forward or backward share of the x sweep (slab.hip); see
+// bfvm_xslab_forward.  xslab_plan: M, segments and lines per tile for an
+// m-voxel slab line (0 beyond reach); xslab_lds: the block's LDS bytes.
+int xslab_plan(int64_t m, int* M, int* K, int* lpw);
+size_t xslab_lds(int M, int K, int lpw, int S, int cs);
+hipError_t launch_xslab(int dtype, bool fwd, void* slab, int64_t m, int S, int64_t l0, int64_t nlines,
+                        const void* invd, const void* r, int64_t x0, const void* cin, void* cout, hipStream_t st);
+
 // Second stage of the per-line sums: out[(a*S + s)*2 + {0,1}] = the sum over
 // the lines L = s (mod S) of axis a (part[a], nlines[a] lines), in line order.
 hipError_t launch_adjoint_line_final(double* const part[3], const int64_t nlines[3], int S, double* out,

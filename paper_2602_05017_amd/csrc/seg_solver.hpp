@@ -217,10 +217,9 @@ __device__ __forceinline__ void seg_forward(C (&v)[M], C r, const Coef& coef, C&
     }
 }
 
-// forward correction t_i = f_i + (prod of coefficients up to i) * carry, then
-// the backward pass with zero carry; GB = product of alpha over the segment
+// forward correction t_i = f_i + (prod of coefficients up to i) * carry
 template <typename C, int M, bool TR, typename Coef>
-__device__ __forceinline__ void seg_middle(C (&v)[M], C r, const Coef& coef, C carry, C& bw, C& GB)
+__device__ __forceinline__ void seg_fwd_correct(C (&v)[M], C r, const Coef& coef, C carry)
 {
     C c = carry;
 #pragma unroll
@@ -229,9 +228,12 @@ __device__ __forceinline__ void seg_middle(C (&v)[M], C r, const Coef& coef, C c
         c = a * c;
         v[k] += c;
     }
-    // Re-read the coefficients below instead of keeping all M of them live
-    // across both loops (they are cheap LDS/L1 reads; registers are not).
-    asm volatile("" ::: "memory");
+}
+
+// the backward pass with zero carry; GB = product of alpha over the segment
+template <typename C, int M, bool TR, typename Coef>
+__device__ __forceinline__ void seg_bwd_local(C (&v)[M], C r, const Coef& coef, C& bw, C& GB)
+{
     bw = 0;
     GB = 1;
 #pragma unroll
@@ -245,6 +247,17 @@ __device__ __forceinline__ void seg_middle(C (&v)[M], C r, const Coef& coef, C c
         GB *= a;
         v[k] = bw;
     }
+}
+
+// the two together (the middle of a whole-line solve)
+template <typename C, int M, bool TR, typename Coef>
+__device__ __forceinline__ void seg_middle(C (&v)[M], C r, const Coef& coef, C carry, C& bw, C& GB)
+{
+    seg_fwd_correct<C, M, TR>(v, r, coef, carry);
+    // Re-read the coefficients below instead of keeping all M of them live
+    // across both loops (they are cheap LDS/L1 reads; registers are not).
+    asm volatile("" ::: "memory");
+    seg_bwd_local<C, M, TR>(v, r, coef, bw, GB);
 }
 
 // backward correction x_i = b_i + (prod of alpha from i to the segment end) * X
