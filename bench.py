@@ -788,43 +788,14 @@ def run_xslab(args):
         f"({alg / (t_slab * 1e-3) / 1e9:.0f} GB/s at 4 moves); as a grid of its own {t_whole_slab:.3f} ms")
     # ---- the 8 slabs chained on one GPU: one stream per slab, events for the
     # block hand-offs (forward slab r after slab r-1, backward after slab r+1)
+    from paper_2602_05017_amd.slabs import chained_x_sweep
     u = torch.empty(p.shape, dtype=torch.float64, device="cuda")
     g.fill_uniform(u, p.seed, 0)
     slabs = [u[:, :, xb[r]:xb[r + 1], :].clone(memory_format=torch.contiguous_format) for r in range(P)]
-    fwd_c = [torch.empty(nl, dtype=torch.float64, device="cuda") for _ in range(P)]
-    bwd_c = [torch.empty(nl, dtype=torch.float64, device="cuda") for _ in range(P)]
     streams = [torch.cuda.Stream() for _ in range(P)]
-    main = torch.cuda.current_stream()
 
     def chained():
-        done_f = [[torch.cuda.Event() for _ in range(NB)] for _ in range(P)]
-        done_b = [[torch.cuda.Event() for _ in range(NB)] for _ in range(P)]
-        start = torch.cuda.Event()
-        start.record(main)
-        for r in range(P):
-            streams[r].wait_event(start)
-        for b in range(NB):
-            l0, l1 = lb[b], lb[b + 1]
-            for r in range(P):
-                with torch.cuda.stream(streams[r]):
-                    if r > 0:
-                        streams[r].wait_event(done_f[r - 1][b])
-                    g.xslab_forward(slabs[r], xb[r], xb[r + 1], l0, l1, fwd_c[r - 1][l0:] if r > 0 else None,
-                                    fwd_c[r][l0:])
-                    done_f[r][b].record(streams[r])
-        for b in range(NB):
-            l0, l1 = lb[b], lb[b + 1]
-            for r in reversed(range(P)):
-                with torch.cuda.stream(streams[r]):
-                    if r < P - 1:
-                        streams[r].wait_event(done_b[r + 1][b])
-                    else:
-                        streams[r].wait_event(done_f[r][b])
-                    g.xslab_backward(slabs[r], xb[r], xb[r + 1], l0, l1, bwd_c[r + 1][l0:] if r < P - 1 else None,
-                                     bwd_c[r][l0:])
-                    done_b[r][b].record(streams[r])
-        for r in range(P):
-            main.wait_stream(streams[r])
+        chained_x_sweep(g, slabs, xb, lb, streams)
 
     chained()
     torch.cuda.synchronize()

@@ -108,3 +108,32 @@ def test_slab_calls_check_their_arguments():
     assert ei.value.code == "EINVAL"
     gb.close()
     g.close()
+
+
+def test_chained_schedule_on_slab_streams_matches_the_oracle():
+    # the schedule the processes would run (paper_2602_05017_amd.slabs):
+    # one stream per slab, an event per (slab, block) hand-off, so slab r
+    # works on block b while slab r + 1 works on block b - 1.  Same result,
+    # bit for bit, as the shares run one after another on one stream, and
+    # the oracle's x sweep of the whole field
+    import torch
+    from paper_2602_05017_amd.slabs import chained_x_sweep
+    p = small_problem((80, 9, 6), 2, seed=941, nsteps=1)
+    g = make_grid(p)
+    u = upload(p, g)
+    xb = [0, 17, 40, 41, 80]
+    nl = 9 * 6 * 2
+    lb = [0, 5, 33, 34, 70, nl]
+    cut = lambda: [u[:, :, xb[r]:xb[r + 1], :].clone(memory_format=torch.contiguous_format) for r in range(4)]
+    par = cut()
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    chained_x_sweep(g, par, xb, lb, streams)
+    seq = cut()
+    chained_x_sweep(g, seq, xb, lb)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(par, seq))
+    ref = np.array(p.field(), dtype=np.float64, copy=True)
+    oracle.sweep(ref, p.h, p.D, p.lam, p.dt, 0)
+    e = rel_err(torch.cat(par, dim=2).cpu().numpy(), ref)[0]
+    assert e <= 1e-12, e
+    g.close()
