@@ -748,9 +748,9 @@ def run_xslab(args):
     # ---- one slab (a middle process), forward then backward over the blocks
     x0, x1 = xb[P // 2], xb[P // 2 + 1]
     m = x1 - x0
-    slab = torch.empty((p.nz, p.ny, m, S), dtype=torch.float64, device="cuda")
-    slab.uniform_(0.0, 1.0, generator=torch.Generator(device="cuda").manual_seed(p.seed))
-    cin = torch.empty(nl, dtype=torch.float64, device="cuda").uniform_(0.0, 1.0)
+    gen = torch.Generator(device="cuda").manual_seed(p.seed)
+    slab = torch.empty((p.nz, p.ny, m, S), dtype=torch.float64, device="cuda").uniform_(0.0, 1.0, generator=gen)
+    cin = torch.empty(nl, dtype=torch.float64, device="cuda").uniform_(0.0, 1.0, generator=gen)
     cout = torch.empty(nl, dtype=torch.float64, device="cuda")
 
     def one_slab():
