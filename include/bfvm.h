@@ -410,7 +410,7 @@ int bfvm_batch_step_adjoint(bfvm_batch b, int32_t count, const int32_t* subset, 
                             double* grad_lambda);
 
 /* Autotuner: picks per (axis, line length, substrates, storage type) class
- * the lines per tile (16, 32, 64) and elements per thread (4, 8, 16), and
+ * the lines per tile (16, 32, 64) and elements per thread (4, 8, 12, 16), and
  * the work per item, by timing the batch step; reuses / writes a JSON cache
  * at cache_path (NULL: no cache), keyed by the GPU architecture and mode.
  * best_ms: the tuned step time.  Runs steps on the fields (their contents
@@ -423,7 +423,7 @@ int bfvm_batch_autotune(bfvm_batch b, const char* cache_path, double* best_ms);
 int bfvm_batch_get_plan(bfvm_batch b, int32_t domain, int32_t axis, int32_t* m, int32_t* lpw);
 
 /* Set a domain axis's plan by hand (the autotuner's choice otherwise):
- * m in {4, 8, 16} (8 at most in persistent mode), lpw in {16, 32, 64},
+ * m in {4, 8, 12, 16} (8 at most in persistent mode), lpw in {16, 32, 64},
  * and the 512 / lpw segments of m elements must cover the line.  Rebuilds
  * the forward program; the next reverse step rebuilds its own.  The
  * transposed sweeps of an M = 16 axis run as M = 8 with half the lines per

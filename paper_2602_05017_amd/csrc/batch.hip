@@ -624,6 +624,7 @@ void launch_group_sweep(int M, int64_t n, hipStream_t s, const BDomain* d, const
     switch (M) {
         case 4: hipLaunchKernelGGL((k_group_sweep<T, C, 4, TR>), grid, block, 0, s, d, it, partials); break;
         case 8: hipLaunchKernelGGL((k_group_sweep<T, C, 8, TR>), grid, block, 0, s, d, it, partials); break;
+        case 12: hipLaunchKernelGGL((k_group_sweep<T, C, 12, TR>), grid, block, 0, s, d, it, partials); break;
         default: hipLaunchKernelGGL((k_group_sweep<T, C, 16, TR>), grid, block, 0, s, d, it, partials); break;
     }
 }
@@ -1049,7 +1050,7 @@ int bfvm_batch_set_plan(bfvm_batch b, int32_t domain, int32_t axis, int32_t m, i
         return bfail(BFVM_ERANGE, "domain or axis");
     if (b->large[domain])
         return bfail(BFVM_ESTATE, "the domain runs its own grid's kernels: set its plan with bfvm_set_plan");
-    if (m != 4 && m != 8 && m != 16) return bfail(BFVM_EINVAL, "m must be 4, 8 or 16");
+    if (m != 4 && m != 8 && m != 12 && m != 16) return bfail(BFVM_EINVAL, "m must be 4, 8, 12 or 16");
     if (m > max_m_for_mode(b->mode)) return bfail(BFVM_EINVAL, "m too large for the batch mode");
     if (lpw != 16 && lpw != 32 && lpw != 64) return bfail(BFVM_EINVAL, "lpw must be 16, 32 or 64");
     BDomain& d = b->doms[domain];
@@ -1076,7 +1077,7 @@ int bfvm_batch_info(bfvm_batch b, int64_t* items, int32_t* launches, int64_t* ch
 //
 // Tunes, for the batch at hand, (1) the tile shape of every (axis, line
 // length, substrate count, storage type) class: lines per tile lpw in
-// {16, 32, 64} with the smallest elements-per-thread M in {4, 8, 16} that
+// {16, 32, 64} with the smallest elements-per-thread M in {4, 8, 12, 16} that
 // still covers the line (K = 512 / lpw segments of M), and (2) the work
 // per item.  Coordinate descent: for each axis, each lpw candidate is
 // applied to every domain where it fits and the whole batch step is timed;

@@ -102,7 +102,11 @@ inline int64_t axis_len(const BDomain& d, int axis) { return axis == 0 ? d.nx : 
 
 inline bool plan_fits(int64_t n, int M, int lpw) { return (int64_t)(kBatchThreads / lpw) * M >= n; }
 
-constexpr int kBatchM[] = {4, 8, 16};
+// M = 12 fills the lines of 65..96 voxels that an 8-segment tile would
+// otherwise hold as 128 slots of 16: 96-domain step 4.70 -> 4.44 ms with
+// {4, 8, 12, 16}; adding 6 and 10 (38 launches per step instead of 26) gave
+// 4.47 ms
+constexpr int kBatchM[] = {4, 8, 12, 16};
 
 // smallest supported elements-per-thread whose K = 512 / lpw segments cover n
 inline int smallest_m(int64_t n, int lpw, int max_m)
@@ -115,14 +119,15 @@ inline int smallest_m(int64_t n, int lpw, int max_m)
 inline int max_m_for_mode(int mode) { return mode == BFVM_BATCH_PERSISTENT ? 8 : 16; }
 
 // Tile shape of a sweep stage: the domain's plan, except that a transposed
-// sweep of M = 16 runs as M = 8 with half the lines per tile (at least 16)
-// where those segments still cover the line.  The transposed M = 16 tiles
-// need 170 VGPRs, one 512-thread block per CU; at M = 8 (115) two fit.
+// sweep of M = 12 or 16 runs as M = 8 with half the lines per tile (at
+// least 16) where those segments still cover the line.  The transposed
+// M = 12 and 16 tiles need 168 and 203 VGPRs, one 512-thread block per CU;
+// at M = 8 (128) two fit.
 inline void tile_shape(const BDomain& d, int axis, bool transposed, int* m, int* lpw)
 {
     *m = d.M[axis];
     *lpw = d.lpw[axis];
-    if (transposed && *m == 16) {
+    if (transposed && *m > 8) {
         const int l = std::max(16, *lpw / 2);
         if (plan_fits(axis_len(d, axis), 8, l)) {
             *m = 8;
