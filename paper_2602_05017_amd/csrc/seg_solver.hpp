@@ -195,6 +195,21 @@ struct RegCoef {        // the segment's M values held in registers
     __device__ __forceinline__ C operator()(int k) const { return b[k]; }
 };
 
+// Workgroup barrier for LDS traffic only: the wave's own LDS accesses are
+// complete (lgkmcnt 0) before it, and the compiler moves no memory access
+// across it.  Unlike __syncthreads it does not wait for the wave's global
+// loads in flight, so global-to-LDS loads can continue through it; their
+// target is read only after an explicit wait for them and a barrier.
+__device__ __forceinline__ void lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// 16 bytes per lane from global memory straight into LDS (no registers):
+// lane l's bytes land at wave_base + 16 * l; wave_base is the same for the
+// whole wave.  Counted by the wave's vector-memory counter like a load.
+__device__ __forceinline__ void load_lds16(const void* src, void* wave_base)
+{
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)wave_base, 16, 0, 0);
+}
+
 // The three register phases of a segment.
 // forward pass with zero carry; G = product of the forward coefficients
 template <typename C, int M, bool TR, typename Coef>
@@ -277,17 +292,26 @@ __device__ __forceinline__ void seg_last(C (&v)[M], C r, const Coef& coef, C X)
 // thread of the block calls this (it holds barriers and shuffles); writer =
 // the thread owns a (segment, line) slot.
 // UNR: see carry_scan (fewer registers for the leader scan where a kernel
-// holds more than one segment's values)
-template <typename C, int M, bool TR, bool PAR, typename Coef, int UNR = 8>
+// holds more than one segment's values).  ASYNC: the block has
+// global-to-LDS loads in flight during the solve; its barriers order LDS
+// only (lds_sync), and the backward terms reuse the forward arrays (2
+// arrays instead of 4; leader scan only): every thread reads its own
+// forward carry before it writes its own backward term.
+template <typename C, int M, bool TR, bool PAR, typename Coef, int UNR = 8, bool ASYNC = false>
 __device__ __forceinline__ void solve_segment(C (&v)[M], int seg, int K, int line, int nl, C r,
                                               const Coef& coef, C* sc, bool writer)
 {
+    static_assert(!(ASYNC && PAR), "two carry arrays with the leader scan only");
+    auto sync = [] {
+        if constexpr (ASYNC) lds_sync();
+        else __syncthreads();
+    };
     const int KP = scan_kp(K, nl, (int)blockDim.x, PAR);
     const int A = KP ? nl * (KP + 1) : K * nl;
     C* sF = sc;
     C* sG = sc + A;
-    C* sB = sc + 2 * A;
-    C* sH = sc + 3 * A;
+    C* sB = ASYNC ? sF : sc + 2 * A;
+    C* sH = ASYNC ? sG : sc + 3 * A;
     const int slot = KP ? line * (KP + 1) + seg : seg * nl + line;
     C f, G;
     seg_forward<C, M, TR>(v, r, coef, f, G);
@@ -295,10 +319,10 @@ __device__ __forceinline__ void solve_segment(C (&v)[M], int seg, int K, int lin
         sF[slot] = f;
         sG[slot] = G;
     }
-    __syncthreads();
+    sync();
     if (KP) carry_scan_par(sF, sG, K, KP, nl, false);
     else if ((int)threadIdx.x < nl) carry_scan<C, UNR>(sF, sG, K, nl, threadIdx.x, false);
-    __syncthreads();
+    sync();
     const C carry = writer ? sF[slot] : (C)0;
     C bw, GB;
     seg_middle<C, M, TR>(v, r, coef, carry, bw, GB);
@@ -306,10 +330,10 @@ __device__ __forceinline__ void solve_segment(C (&v)[M], int seg, int K, int lin
         sB[slot] = bw;
         sH[slot] = GB;
     }
-    __syncthreads();
+    sync();
     if (KP) carry_scan_par(sB, sH, K, KP, nl, true);
     else if ((int)threadIdx.x < nl) carry_scan<C, UNR>(sB, sH, K, nl, threadIdx.x, true);
-    __syncthreads();
+    sync();
     const C X = writer ? sB[slot] : (C)0;
     seg_last<C, M>(v, r, coef, X);
 }

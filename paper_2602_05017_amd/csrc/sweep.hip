@@ -327,18 +327,27 @@ __global__ __launch_bounds__(1024) void k_sweep_seg_strided(const T* in, T* out,
 // LDS.  Tiles as kind 1 (lanes over neighbouring lines, waves over
 // segments), with M values of x and M of y per thread; COEF 1 (LDS copy of
 // the table) or 2 (compressed rows).
-template <typename T, typename C, int M, int COEF, int UNR>
+//
+// DMA: the block's gradient tile ([n planes][lpw lines] of T, from byte gb_off
+// of the block's LDS) is fetched straight into LDS with 16-byte global-to-LDS
+// loads issued before the forward solve, so the gradient is in flight while x
+// is recomputed instead of being requested after it; the solves then use two
+// carry arrays instead of four, and the x end values and the sums go through
+// the tile's space once it has been read.  Needs 16-byte aligned rows and
+// lines that fill whole 16-byte chunks (checked by the launcher).
+template <typename T, typename C, int M, int COEF, int UNR, bool DMA>
 __global__ __launch_bounds__(512, 4) void k_adj_z_fused(const T* zin, T* grad, AxisGeom g,
                                                         const C* __restrict__ invd, const C* __restrict__ rr,
                                                         int lpw, int SP, FastDiv divS, const C* __restrict__ comp,
-                                                        int H, double* __restrict__ part)
+                                                        int H, double* __restrict__ part, int gb_off)
 {
     uint32_t bx, by;
     xcd_tile(bx, by);
     extern __shared__ __align__(16) unsigned char smem[];
     const int K = blockDim.x / lpw;
     C* sc = reinterpret_cast<C*>(smem);
-    C* tab = sc + 4 * scan_slots(K, lpw, (int)blockDim.x, false);
+    C* tab = sc + (DMA ? 2 : 4) * scan_slots(K, lpw, (int)blockDim.x, false);
+    T* gb = reinterpret_cast<T*>(smem + gb_off);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int line = lane % lpw;
@@ -355,6 +364,7 @@ __global__ __launch_bounds__(512, 4) void k_adj_z_fused(const T* zin, T* grad, A
     const int64_t base = (g.o0 + (int64_t)by) * g.outer_stride + g.p0 + pa + i0 * st;
     const C r = rr[s];
     const C prev = (i0 > 0 && last >= 0) ? invd[(i0 - 1) * S + s] : (C)0;
+    const int64_t p_first = (int64_t)bx * lpw;
     C x[M], y[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) x[k] = (C)zin[base + (k <= last ? k : last) * st];
@@ -362,15 +372,49 @@ __global__ __launch_bounds__(512, 4) void k_adj_z_fused(const T* zin, T* grad, A
     // stay live through the second solve
     auto solve_both = [&](const auto& coef) {
         using Cf = std::decay_t<decltype(coef)>;
-        solve_segment<C, M, false, false, Cf, UNR>(x, seg, K, line, lpw, r, coef, sc, true);
-        // opaque pointer and bound: the gradient's addresses are formed here
-        // instead of being kept live through the first solve
-        const T* gp = grad + base;
-        int lastv = (int)(last < M ? last : M);
-        asm volatile("" : "+v"(gp), "+v"(lastv));
+        if constexpr (DMA) {
+            // chunk c = plane * lpw/E + part of the plane's row, 16 bytes; the
+            // tile of K*M planes is 512 * sizeof(T) chunks, sizeof(T) per
+            // thread, a wave's instruction filling 64 consecutive ones (lane
+            // l at 16 * l bytes past its base).  Every lane issues every load
+            // (planes past the line end and chunks past the last line read a
+            // clamped chunk), so the count in flight is fixed and the solve
+            // below waits for the x values alone.
+            constexpr int E = 16 / (int)sizeof(T);
+            const int chs = __builtin_ctz((unsigned)(lpw / E));   // chunks per row: a power of two
+            // the x values first (the compiler's own wait before their use
+            // would otherwise count the tile's loads too): vmcnt(0) alone
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+            const int64_t cmax = (g.inner - p_first) / E - 1;   // last chunk within the lines
+            const T* src0 = grad + (g.o0 + (int64_t)by) * g.outer_stride + g.p0 + p_first;
 #pragma unroll
-        for (int k = 0; k < M; ++k) y[k] = (C)gp[(k <= lastv ? k : lastv) * st];
-        solve_segment<C, M, true, false, Cf, UNR>(y, seg, K, line, lpw, r, coef, sc, true);
+            for (int q = 0; q < (int)sizeof(T); ++q) {
+                const int j = (q * (int)(blockDim.x >> 6) + wave) * 64;
+                const int c = j + lane;
+                const int pl = min(c >> chs, (int)g.n - 1);
+                const int cc = (int)min((int64_t)(c & ((1 << chs) - 1)), cmax);
+                load_lds16(src0 + pl * st + cc * E, gb + (int64_t)j * E);
+            }
+        }
+        solve_segment<C, M, false, false, Cf, UNR, DMA>(x, seg, K, line, lpw, r, coef, sc, true);
+        int lastv = (int)(last < M ? last : M);
+        if constexpr (DMA) {
+            // this wave's chunks have landed once its memory counter is 0,
+            // every wave's after the barrier
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+            __syncthreads();
+            const T* gr = gb + (int)(pa - p_first);
+#pragma unroll
+            for (int k = 0; k < M; ++k) y[k] = (C)gr[((int)i0 + (k <= lastv ? k : lastv)) * lpw];
+        } else {
+            // opaque pointer and bound: the gradient's addresses are formed
+            // here instead of being kept live through the first solve
+            const T* gp = grad + base;
+            asm volatile("" : "+v"(gp), "+v"(lastv));
+#pragma unroll
+            for (int k = 0; k < M; ++k) y[k] = (C)gp[(k <= lastv ? k : lastv) * st];
+        }
+        solve_segment<C, M, true, false, Cf, UNR, DMA>(y, seg, K, line, lpw, r, coef, sc, true);
     };
     if constexpr (COEF == 1) {
         stage_table<C, M>(tab, invd, (uint32_t)g.n, (uint32_t)(K * M), (uint32_t)S, (uint32_t)SP, divS);
@@ -395,7 +439,8 @@ __global__ __launch_bounds__(512, 4) void k_adj_z_fused(const T* zin, T* grad, A
     // x at the segment's ends for the neighbouring segments (the carry
     // arrays hold at least two doubles per slot)
     const int slot = seg * lpw + line;
-    double* xfirst = reinterpret_cast<double*>(sc);
+    C* sums = DMA ? reinterpret_cast<C*>(gb) : sc;   // room for two doubles per slot
+    double* xfirst = reinterpret_cast<double*>(sums);
     double* xlast = xfirst + K * lpw;
     __syncthreads();   // the solves' last reads of the carry arrays are done
     xfirst[slot] = (double)(T)x[0];
@@ -420,8 +465,7 @@ __global__ __launch_bounds__(512, 4) void k_adj_z_fused(const T* zin, T* grad, A
             xc = xn;
         }
     }
-    const int64_t p_first = (int64_t)bx * lpw;
-    line_sums_store<C>(a0, a1, seg, K, line, lpw, sc, false, true, part, (int64_t)by * g.inner + p_first,
+    line_sums_store<C>(a0, a1, seg, K, line, lpw, sums, false, true, part, (int64_t)by * g.inner + p_first,
                        (int)min((int64_t)lpw, g.inner - p_first));
 }
 
@@ -1468,6 +1512,26 @@ static hipError_t launch_adj_z_fused_t(const AxisGeom& g, const void* zin, void*
     const bool comp_ok = comp && compH >= 0 && (g.n - 1) / M >= nh;
     const size_t ctab = comp_ok ? (size_t)g.S * (nh + 3) * (M + 1) * sizeof(C) : 0;
     const bool use_comp = ctab > 0 && scan + ctab <= (size_t)max_lds() && (!lds_tab || tab > (48u << 10));
+    int coefk = use_comp ? 2 : (lds_tab ? 1 : 0);
+    if (!coefk) return hipErrorNotSupported;
+    // gradient tile through LDS (DMA form) where the rows are 16-byte aligned
+    // and two blocks still fit a CU; the compressed rows leave it more room
+    constexpr int E = 16 / (int)sizeof(T);
+    const bool dma_ok = (g.stride * (int64_t)sizeof(T)) % 16 == 0 &&
+                        (g.outer == 1 || (g.outer_stride * (int64_t)sizeof(T)) % 16 == 0) && g.p0 == 0 &&
+                        g.o0 == 0 && g.inner % E == 0 && reinterpret_cast<uintptr_t>(grad) % 16 == 0;
+    // the tile of K*M planes (also room for the x end values and the sums,
+    // two doubles per slot)
+    const size_t gbytes = (size_t)K * M * lpw * sizeof(T);
+    auto gb_at = [&](int ck) { return (scan / 2 + (ck == 2 ? ctab : tab) + 15) & ~(size_t)15; };
+    const size_t half = (size_t)max_lds() / 2;
+    bool dma = false;
+    if (dma_ok) {
+        if (gb_at(coefk) + gbytes <= half) dma = true;
+        else if (coefk == 1 && ctab > 0 && gb_at(2) + gbytes <= half) { coefk = 2; dma = true; }
+    }
+    const int gb_off = dma ? (int)gb_at(coefk) : 0;
+    const size_t lds = dma ? gb_at(coefk) + gbytes : scan + (coefk == 2 ? ctab : tab);
     const dim3 grid((unsigned)ceil_div(g.inner, lpw), (unsigned)g.outer);
     const FastDiv dS((uint32_t)g.S);
     const T* zi = static_cast<const T*>(zin);
@@ -1475,14 +1539,11 @@ static hipError_t launch_adj_z_fused_t(const AxisGeom& g, const void* zin, void*
     const C* cf = static_cast<const C*>(invd);
     const C* rr = static_cast<const C*>(r);
     const C* cc = static_cast<const C*>(comp);
-    if (use_comp)
-        hipLaunchKernelGGL((k_adj_z_fused<T, C, M, 2, kAdjZUnr>), grid, dim3(threads), scan + ctab, st, zi, gr, g, cf, rr, lpw,
-                           SP, dS, cc, compH, part);
-    else if (lds_tab)
-        hipLaunchKernelGGL((k_adj_z_fused<T, C, M, 1, kAdjZUnr>), grid, dim3(threads), scan + tab, st, zi, gr, g, cf, rr, lpw,
-                           SP, dS, cc, compH, part);
-    else
-        return hipErrorNotSupported;
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, dim3(threads), lds, st, zi, gr, g, cf, rr, lpw, SP, dS, cc, compH, part, gb_off);
+    };
+    if (coefk == 2) dma ? go(k_adj_z_fused<T, C, M, 2, kAdjZUnr, true>) : go(k_adj_z_fused<T, C, M, 2, kAdjZUnr, false>);
+    else dma ? go(k_adj_z_fused<T, C, M, 1, kAdjZUnr, true>) : go(k_adj_z_fused<T, C, M, 1, kAdjZUnr, false>);
     return hipGetLastError();
 }
 

@@ -246,18 +246,23 @@ def test_backward_uses_its_own_forward_params_after_another_forward_on_the_grid(
 
 @pytest.mark.parametrize("nz", [64, 500, 512, 513, 600])
 @pytest.mark.parametrize("dtype", ["f64", "f32", "f32fast"])
-def test_reverse_step_z_pass_fused_and_two_kernel(nz, dtype):
+@pytest.mark.parametrize("nx", [5, 8])
+def test_reverse_step_z_pass_fused_and_two_kernel(nx, nz, dtype):
     # z lines of up to 512 voxels run the z recomputation and the z
     # transposed sweep as one kernel (k_adj_z_fused: the z output formed and
     # consumed in registers); longer lines run the two kernels with the
-    # workspace between them.  Both against the oracle's adjoint of the
-    # state and gradient the GPU holds: the gradient at the storage form's
-    # bar, dL/dD and dL/dlambda within their normwise bars; the kernel names
-    # the profiler records show which form ran
+    # workspace between them.  The fused kernel fetches the gradient tile
+    # straight into LDS (last template argument true) where the z-planes'
+    # rows are 16-byte aligned and the lines fill whole 16-byte chunks: nx =
+    # 8 (48 values per plane) in every storage form, nx = 5 (30) in FP64
+    # only.  Every form against the oracle's adjoint of the state and
+    # gradient the GPU holds: the gradient at the storage form's bar, dL/dD
+    # and dL/dlambda within their normwise bars; the kernel names the
+    # profiler records show which form ran
     import torch
     from torch.profiler import ProfilerActivity, profile
     from gpu_helpers import oracle_adjoint, param_grad_bars
-    p = small_problem((5, 3, nz), 2, seed=810 + nz, nsrc=30, ndir=8)
+    p = small_problem((nx, 3, nz), 2, seed=810 + nz + nx, nsrc=30, ndir=8)
     p.dtype = dtype
     rng = np.random.default_rng(nz)
     gin = (rng.random(p.shape) - 0.5).astype(np.float64 if dtype == "f64" else np.float32)
@@ -271,7 +276,12 @@ def test_reverse_step_z_pass_fused_and_two_kernel(nz, dtype):
     names = {e.name for e in prof.events()}
     state = g.read_field(u)
     g.close()
-    assert any("k_adj_z_fused" in n for n in names) == (nz <= 512), sorted(names)
+    fused = [n for n in names if "k_adj_z_fused" in n]
+    assert bool(fused) == (nz <= 512), sorted(names)
+    inner = nx * 3 * 2
+    dma = nz <= 512 and inner % (2 if dtype == "f64" else 4) == 0
+    assert any("1, true>" in n for n in fused) == dma and any("1, false>" in n for n in fused) == (
+        nz <= 512 and not dma), fused
     rg, rD, rL = oracle_adjoint(p, state, gin)
     barD, barL = param_grad_bars(p, state, gin)
     e = rel_err(gg.double().cpu().numpy(), rg)[0]
