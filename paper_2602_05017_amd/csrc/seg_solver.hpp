@@ -385,8 +385,9 @@ __device__ __forceinline__ void seg_adjoint_sums(const C (&y)[M], const T* xp, i
 // order and writes each valid line's pair to out[2 L], L = L0 + line.  The
 // carry arrays sc of solve_segment are reused (they hold at least 2 doubles
 // per slot in either layout), so this must follow the solve; every thread
-// of the block calls it.
-template <typename C>
+// of the block calls it.  LDSB: its barriers order LDS only (lds_sync), so
+// global stores issued before it stay in flight.
+template <typename C, bool LDSB = false>
 __device__ __forceinline__ void line_sums_store(double a0, double a1, int seg, int K, int line, int nl, C* sc,
                                                 bool par, bool writer, double* out, int64_t L0, int nvalid)
 {
@@ -394,13 +395,17 @@ __device__ __forceinline__ void line_sums_store(double a0, double a1, int seg, i
     const int A = KP ? nl * (KP + 1) : K * nl;
     double* s0 = reinterpret_cast<double*>(sc);
     double* s1 = s0 + A;
-    __syncthreads();   // the solve's last reads of the carry arrays are done
+    auto sync = [] {
+        if constexpr (LDSB) lds_sync();
+        else __syncthreads();
+    };
+    sync();   // the solve's last reads of the carry arrays are done
     if (writer) {
         const int slot = KP ? line * (KP + 1) + seg : seg * nl + line;
         s0[slot] = a0;
         s1[slot] = a1;
     }
-    __syncthreads();
+    sync();
     const int l = (int)threadIdx.x;
     if (l < nl && l < nvalid) {
         double b0 = 0.0, b1 = 0.0;

@@ -311,6 +311,61 @@ __global__ __launch_bounds__(1024) void k_sweep_seg_strided(const T* in, T* out,
     }
 }
 
+// A segment's cnt real values to p[k * st].  The opaque pointer makes the
+// compiler form the M addresses here instead of keeping the load addresses
+// live through the solve; it stays a global pointer, so the stores are
+// global stores, counted by the memory counter only (a flat store would
+// also hold up every later wait for LDS accesses).
+template <typename T, typename C, int M>
+__device__ __forceinline__ void store_seg(const C (&v)[M], T* gp, int64_t st, int cnt)
+{
+    auto p = (__attribute__((address_space(1))) T*)gp;
+    asm volatile("" : "+v"(p));
+    if (cnt == M) {
+#pragma unroll
+        for (int k = 0; k < M; ++k) p[k * st] = (T)v[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < M; ++k)
+            if (k < cnt) p[k * st] = (T)v[k];
+    }
+}
+
+// The block's tile [K*M planes][lpw lines] of T (lines of its tile
+// contiguous, planes st apart) into LDS at gb with 16-byte global-to-LDS
+// loads, which take no registers: chunk c = plane * lpw/E + part of the
+// plane's row (E = 16 / sizeof(T) values), 512 * sizeof(T) chunks, sizeof(T)
+// per thread of the 512, a wave's instruction filling 64 consecutive ones
+// (lane l at 16 * l bytes past its base).  Every lane issues every load:
+// planes past the line end and chunks past the last line read a clamped
+// chunk, so the count in flight is fixed and a later wait for values loaded
+// before these counts them exactly.  Tile line l (a multiple of E) starts at
+// src0 + lineoff(l) at plane 0, its E lines contiguous; nlines = lines from
+// the tile's first to the last line of the grid (at least E, a multiple of
+// E).  The tile is complete once the wave's memory counter is 0 and then,
+// for every wave's part, after a barrier.
+template <typename T, typename F>
+__device__ __forceinline__ void fetch_tile_lds(T* gb, const T* src0, F lineoff, int64_t st, int n, int lpw,
+                                               int64_t nlines)
+{
+    constexpr int E = 16 / (int)sizeof(T);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int chs = __builtin_ctz((unsigned)(lpw / E));   // chunks per row: a power of two
+    const int64_t cmax = nlines / E - 1;
+#pragma unroll
+    for (int q = 0; q < (int)sizeof(T); ++q) {
+        const int j = (q * (int)(blockDim.x >> 6) + wave) * 64;
+        const int c = j + lane;
+        const int pl = min(c >> chs, n - 1);
+        const int cc = (int)min((int64_t)(c & ((1 << chs) - 1)), cmax);
+        load_lds16(src0 + lineoff(cc * E) + pl * st, gb + (int64_t)j * E);
+    }
+}
+
+// vmcnt(0) alone: the wave's vector-memory loads (and global-to-LDS loads)
+// are complete
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // ------------------------------- reverse step: z recomputation + z transposed
 //
 // The z axis of the reverse step in one pass.  The reverse step needs the
@@ -373,35 +428,18 @@ __global__ __launch_bounds__(512, 4) void k_adj_z_fused(const T* zin, T* grad, A
     auto solve_both = [&](const auto& coef) {
         using Cf = std::decay_t<decltype(coef)>;
         if constexpr (DMA) {
-            // chunk c = plane * lpw/E + part of the plane's row, 16 bytes; the
-            // tile of K*M planes is 512 * sizeof(T) chunks, sizeof(T) per
-            // thread, a wave's instruction filling 64 consecutive ones (lane
-            // l at 16 * l bytes past its base).  Every lane issues every load
-            // (planes past the line end and chunks past the last line read a
-            // clamped chunk), so the count in flight is fixed and the solve
-            // below waits for the x values alone.
-            constexpr int E = 16 / (int)sizeof(T);
-            const int chs = __builtin_ctz((unsigned)(lpw / E));   // chunks per row: a power of two
             // the x values first (the compiler's own wait before their use
-            // would otherwise count the tile's loads too): vmcnt(0) alone
-            __builtin_amdgcn_s_waitcnt(0x0F70);
-            const int64_t cmax = (g.inner - p_first) / E - 1;   // last chunk within the lines
-            const T* src0 = grad + (g.o0 + (int64_t)by) * g.outer_stride + g.p0 + p_first;
-#pragma unroll
-            for (int q = 0; q < (int)sizeof(T); ++q) {
-                const int j = (q * (int)(blockDim.x >> 6) + wave) * 64;
-                const int c = j + lane;
-                const int pl = min(c >> chs, (int)g.n - 1);
-                const int cc = (int)min((int64_t)(c & ((1 << chs) - 1)), cmax);
-                load_lds16(src0 + pl * st + cc * E, gb + (int64_t)j * E);
-            }
+            // would otherwise count the tile's loads too)
+            wait_vm();
+            fetch_tile_lds<T>(gb, grad + (g.o0 + (int64_t)by) * g.outer_stride + g.p0 + p_first,
+                              [](int l) { return (int64_t)l; }, st, (int)g.n, lpw, g.inner - p_first);
         }
         solve_segment<C, M, false, false, Cf, UNR, DMA>(x, seg, K, line, lpw, r, coef, sc, true);
         int lastv = (int)(last < M ? last : M);
         if constexpr (DMA) {
             // this wave's chunks have landed once its memory counter is 0,
             // every wave's after the barrier
-            __builtin_amdgcn_s_waitcnt(0x0F70);
+            wait_vm();
             __syncthreads();
             const T* gr = gb + (int)(pa - p_first);
 #pragma unroll
@@ -426,26 +464,20 @@ __global__ __launch_bounds__(512, 4) void k_adj_z_fused(const T* zin, T* grad, A
         __syncthreads();
         solve_both(LdsCoef<C>{tab + s * cr.SPr + cr.row(seg) * (M + 1), prev});
     }
-    T* op = grad + base;
-    asm volatile("" : "+v"(op));
-    if (cnt == M) {
-#pragma unroll
-        for (int k = 0; k < M; ++k) op[k * st] = (T)y[k];
-    } else {
-#pragma unroll
-        for (int k = 0; k < M; ++k)
-            if (k < cnt) op[k * st] = (T)y[k];
-    }
+    // stored before the sums (after them, with x and y both live through the
+    // exchange, the kernel spills 17-19 VGPRs); the barriers below order LDS
+    // only, so the stores stay in flight through them
+    store_seg<T, C, M>(y, grad + base, st, cnt);
     // x at the segment's ends for the neighbouring segments (the carry
     // arrays hold at least two doubles per slot)
     const int slot = seg * lpw + line;
     C* sums = DMA ? reinterpret_cast<C*>(gb) : sc;   // room for two doubles per slot
     double* xfirst = reinterpret_cast<double*>(sums);
     double* xlast = xfirst + K * lpw;
-    __syncthreads();   // the solves' last reads of the carry arrays are done
+    lds_sync();   // the solves' last reads of the carry arrays are done
     xfirst[slot] = (double)(T)x[0];
     xlast[slot] = (double)(T)x[M - 1];
-    __syncthreads();
+    lds_sync();
     const bool left = i0 > 0 && last >= 0;
     double xl = left ? xlast[slot - lpw] : 0.0;
     double a0 = 0.0, a1 = 0.0;
@@ -465,8 +497,112 @@ __global__ __launch_bounds__(512, 4) void k_adj_z_fused(const T* zin, T* grad, A
             xc = xn;
         }
     }
-    line_sums_store<C>(a0, a1, seg, K, line, lpw, sums, false, true, part, (int64_t)by * g.inner + p_first,
-                       (int)min((int64_t)lpw, g.inner - p_first));
+    line_sums_store<C, true>(a0, a1, seg, K, line, lpw, sums, false, true, part, (int64_t)by * g.inner + p_first,
+                             (int)min((int64_t)lpw, g.inner - p_first));
+}
+
+// ------------------------- reverse step: transposed sweep, sums from an LDS tile
+//
+// The transposed sweep of y (or z) lines of up to 512 voxels with the
+// reverse step's per-line sums y.(L_N x) and y.x, x being the forward
+// output xf on the same lines (in the storage type).  The strided kernel
+// reads x after its solve, so those loads start only when the solve ends;
+// here the block fetches its x tile into LDS with global-to-LDS loads issued
+// before the solve (fetch_tile_lds), in flight while it runs, and the sums
+// read x and its neighbours from LDS.  Tiles as k_adj_z_fused: M = 16, K =
+// the power of two >= n/16 (at least 8) segments, 512/K neighbouring lines,
+// two blocks per CU; the solve's barriers order LDS only and its scans use
+// two carry arrays; the sums go through the tile's space once it is read.
+// XROWS: x lines (line L = substrate L % S of row L / S, its elements S
+// apart in the row's n*S run; g.inner = rows * S, one outer index), the
+// tile's lpw lines being lpw / S whole rows.
+template <typename T, typename C, int M, int COEF, bool XROWS>
+__global__ __launch_bounds__(512, 4) void k_adj_tr_tile(const T* in, T* out, AxisGeom g, const C* __restrict__ invd,
+                                                        const C* __restrict__ rr, int lpw, int SP, FastDiv divS,
+                                                        const C* __restrict__ comp, int H, const T* __restrict__ xf,
+                                                        double* __restrict__ part, int gb_off)
+{
+    uint32_t bx, by;
+    xcd_tile(bx, by);
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int K = blockDim.x / lpw;
+    C* sc = reinterpret_cast<C*>(smem);
+    C* tab = sc + 2 * scan_slots(K, lpw, (int)blockDim.x, false);
+    T* gb = reinterpret_cast<T*>(smem + gb_off);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int line = lane % lpw;
+    const int seg = wave * (64 / lpw) + lane / lpw;
+    const int64_t p = (int64_t)bx * lpw + line;
+    const bool valid = p < g.inner;
+    const int64_t pa = valid ? p : g.inner - 1;   // clamped line for padding loads
+    const int S = g.S;
+    const int s = (int)((g.p0 + pa) % S);
+    const int64_t i0 = (int64_t)seg * M;
+    const int64_t last = g.n - 1 - i0;            // slots k > last are padding
+    const int cnt = !valid || last < 0 ? 0 : (last >= M ? M : (int)last + 1);
+    const int64_t st = g.stride;
+    const int64_t p_first = (int64_t)bx * lpw;
+    const int64_t nS = g.n * S;
+    // first element of the tile's first line, and of line pa
+    const int64_t row0 = XROWS ? (int64_t)divS.div((uint32_t)p_first) * nS
+                               : (g.o0 + (int64_t)by) * g.outer_stride + g.p0 + p_first;
+    const int64_t base = (XROWS ? (int64_t)divS.div((uint32_t)pa) * nS + s : row0 + (pa - p_first)) + i0 * st;
+    const C r = rr[s];
+    const C prev = (i0 > 0 && last >= 0) ? invd[(i0 - 1) * S + s] : (C)0;
+    C y[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) y[k] = (C)in[base + (k <= last ? k : last) * st];
+    auto solve = [&](const auto& coef) {
+        using Cf = std::decay_t<decltype(coef)>;
+        wait_vm();   // the gradient values first, then the x tile in flight
+        if constexpr (XROWS)
+            fetch_tile_lds<T>(gb, xf + row0, [&](int l) {
+                const int r = (int)divS.div((uint32_t)l);
+                return (int64_t)r * nS + (l - r * S);
+            }, st,
+                              (int)g.n, lpw, g.inner - p_first);
+        else
+            fetch_tile_lds<T>(gb, xf + row0, [](int l) { return (int64_t)l; }, st, (int)g.n, lpw, g.inner - p_first);
+        solve_segment<C, M, true, false, Cf, 8, true>(y, seg, K, line, lpw, r, coef, sc, true);
+    };
+    if constexpr (COEF == 1) {
+        stage_table<C, M>(tab, invd, (uint32_t)g.n, (uint32_t)(K * M), (uint32_t)S, (uint32_t)SP, divS);
+        __syncthreads();
+        solve(LdsCoef<C>{tab + s * SP + seg * (M + 1), prev});
+    } else {
+        const CompRows<M> cr(H, (int)g.n);
+        build_comp_rows<C, M>(tab, comp, H, (int)g.n, S, cr);
+        __syncthreads();
+        solve(LdsCoef<C>{tab + s * cr.SPr + cr.row(seg) * (M + 1), prev});
+    }
+    wait_vm();
+    __syncthreads();   // every wave's part of the x tile has landed
+    double a0 = 0.0, a1 = 0.0;
+    if (cnt > 0) {
+        const T* xr = gb + (int)(pa - p_first);
+        const int ib = (int)i0, lst = (int)last;
+        const bool left = ib > 0;
+        double xl = left ? (double)xr[(ib - 1) * lpw] : 0.0;
+        double xc = (double)xr[ib * lpw];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const double xn = k + 1 <= lst ? (double)xr[(ib + k + 1) * lpw] : 0.0;
+            double lx = 0.0;
+            if (k > 0 || left) lx += xc - xl;
+            if (k + 1 <= lst) lx += xc - xn;
+            if (k <= lst) {
+                a0 += (double)y[k] * lx;
+                a1 += (double)y[k] * xc;
+            }
+            xl = xc;
+            xc = xn;
+        }
+    }
+    line_sums_store<C>(a0, a1, seg, K, line, lpw, reinterpret_cast<C*>(gb), false, true, part,
+                       (int64_t)by * g.inner + p_first, (int)min((int64_t)lpw, g.inner - p_first));
+    // the stores last: the barriers above would otherwise wait for them
+    store_seg<T, C, M>(y, out + base, st, cnt);
 }
 
 // ------------------------------------------ kind 5 (y/z, lines in two parts)
@@ -1470,16 +1606,6 @@ static hipError_t launch_typed(const SweepPlan& p, const AxisGeom& g, const void
     }
 }
 
-template <typename T, typename C>
-static hipError_t launch_dir(bool transposed, const SweepPlan& plan, const AxisGeom& g, const void* in, void* out,
-                             const void* invd, const void* r, const void* comp, int compH, hipStream_t st,
-                             const AdjSums& red)
-{
-    if (!transposed) return launch_typed<T, C, false, false>(plan, g, in, out, invd, r, comp, compH, st, red);
-    if (red.part) return launch_typed<T, C, true, true>(plan, g, in, out, invd, r, comp, compH, st, red);
-    return launch_typed<T, C, true, false>(plan, g, in, out, invd, r, comp, compH, st, red);
-}
-
 constexpr int kAdjZUnr = 1;
 
 // z lines of up to 512 voxels: M = 16 values of x and of y per thread, K =
@@ -1573,6 +1699,95 @@ hipError_t launch_adj_z_fused(int dtype, const AxisGeom& g, const void* zin, voi
         case DT_F32_FAST: return launch_adj_z_fused_t<float, float>(g, zin, grad, invd, r, comp, compH, part, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+// Transposed sweep with the sums from an LDS x tile (k_adj_tr_tile), the
+// reverse step's form of that sweep where it applies: lines of up to 512
+// voxels, two blocks per CU within the LDS, and tile rows of whole 16-byte
+// chunks, 16-byte aligned: for y and z lines, lines filling whole chunks;
+// for x lines (as rows of S substrates), S a multiple of the values per
+// chunk and the tiles whole rows.  It replaces the strided kernel of the
+// axis's plan (kind 1, or kind 5, whose transposed sweeps run as kind 1; x
+// rows: kind 3), whose per-thread access pattern it keeps; the row-tile
+// kinds for x (2, 4) keep their own kernels.  Elsewhere
+// hipErrorNotSupported before any launch: the caller runs the plan's kernel.
+template <typename T, typename C>
+static hipError_t launch_adj_tr_tile_t(int kind, const AxisGeom& g0, const void* in, void* out, const void* invd,
+                                       const void* r, const void* comp, int compH, const void* xf, double* part,
+                                       hipStream_t st)
+{
+    constexpr int M = 16;
+    constexpr int64_t E = 16 / (int64_t)sizeof(T), es = sizeof(T);
+    const int K = adj_z_fused_k(g0.n);
+    if (!K || g0.p0 != 0 || g0.o0 != 0 || reinterpret_cast<uintptr_t>(xf) % 16) return hipErrorNotSupported;
+    if (g0.axis == 0 ? kind != PLAN_SEG_XROWS : kind != PLAN_SEG_STRIDED && kind != PLAN_SEG_HALVES)
+        return hipErrorNotSupported;
+    const int lpw = 512 / K;
+    const bool xrows = g0.axis == 0;
+    AxisGeom g = g0;
+    if (xrows) {
+        // every (row, substrate) a line: one outer index over rows * S lines
+        const int64_t lines = g0.inner * g0.outer;
+        if (g0.S % E || lpw % g0.S || (g0.n * g0.S * es) % 16 || lines >= (1ll << 31) ||
+            lines * g0.S > (1ll << 40))
+            return hipErrorNotSupported;
+        g.inner = lines;
+        g.outer = 1;
+    } else if (g.outer > 65535 || (g.stride * es) % 16 || (g.outer > 1 && (g.outer_stride * es) % 16) ||
+               g.inner % E) {
+        return hipErrorNotSupported;
+    }
+    const int threads = 512;
+    const size_t scan2 = 2 * (size_t)scan_slots(K, lpw, threads, false) * sizeof(C);
+    const int period = sizeof(C) == 8 ? 16 : 32;
+    const int spw = 64 / lpw;
+    const int KM1 = K * (M + 1);
+    const int SP = KM1 + (((spw - KM1) % period) + period) % period;
+    const size_t tab = (size_t)g.S * SP * sizeof(C);
+    const int64_t KMS = (int64_t)K * M * g.S;
+    const bool tab_ok = KMS < (1 << 24) && KMS * g.S <= (1ll << 40);
+    const int nh = compH >= 0 ? (compH + M - 1) / M : 0;
+    const bool comp_ok = comp && compH >= 0 && (g.n - 1) / M >= nh;
+    const size_t ctab = comp_ok ? (size_t)g.S * (nh + 3) * (M + 1) * sizeof(C) : 0;
+    const size_t gbytes = (size_t)K * M * lpw * sizeof(T);   // also room for the sums
+    const size_t half = (size_t)max_lds() / 2;
+    auto gb_at = [&](size_t coefb) { return (scan2 + coefb + 15) & ~(size_t)15; };
+    // the compressed rows where they fit (less to stage), else the table
+    int coefk = 0;
+    if (ctab > 0 && gb_at(ctab) + gbytes <= half) coefk = 2;
+    else if (tab_ok && gb_at(tab) + gbytes <= half) coefk = 1;
+    if (!coefk) return hipErrorNotSupported;
+    const size_t at = gb_at(coefk == 2 ? ctab : tab);
+    const dim3 grid((unsigned)ceil_div(g.inner, lpw), (unsigned)g.outer);
+    const FastDiv dS((uint32_t)g.S);
+    const T* ip = static_cast<const T*>(in);
+    T* op = static_cast<T*>(out);
+    const C* cf = static_cast<const C*>(invd);
+    const C* rr = static_cast<const C*>(r);
+    const C* cc = static_cast<const C*>(comp);
+    const T* xp = static_cast<const T*>(xf);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, dim3(threads), at + gbytes, st, ip, op, g, cf, rr, lpw, SP, dS, cc, compH, xp,
+                           part, (int)at);
+    };
+    if (xrows) coefk == 2 ? go(k_adj_tr_tile<T, C, M, 2, true>) : go(k_adj_tr_tile<T, C, M, 1, true>);
+    else coefk == 2 ? go(k_adj_tr_tile<T, C, M, 2, false>) : go(k_adj_tr_tile<T, C, M, 1, false>);
+    return hipGetLastError();
+}
+
+template <typename T, typename C>
+static hipError_t launch_dir(bool transposed, const SweepPlan& plan, const AxisGeom& g, const void* in, void* out,
+                             const void* invd, const void* r, const void* comp, int compH, hipStream_t st,
+                             const AdjSums& red)
+{
+    if (!transposed) return launch_typed<T, C, false, false>(plan, g, in, out, invd, r, comp, compH, st, red);
+    if (red.part) {
+        const hipError_t e =
+            launch_adj_tr_tile_t<T, C>(plan.kind, g, in, out, invd, r, comp, compH, red.x, red.part, st);
+        if (e != hipErrorNotSupported) return e;
+        return launch_typed<T, C, true, true>(plan, g, in, out, invd, r, comp, compH, st, red);
+    }
+    return launch_typed<T, C, true, false>(plan, g, in, out, invd, r, comp, compH, st, red);
 }
 
 hipError_t launch_sweep(int dtype, bool transposed, const SweepPlan& plan, const AxisGeom& g,

@@ -287,3 +287,80 @@ def test_reverse_step_z_pass_fused_and_two_kernel(nx, nz, dtype):
     e = rel_err(gg.double().cpu().numpy(), rg)[0]
     assert e <= {"f64": 1e-12, "f32": 1e-5, "f32fast": 1e-5}[dtype], (nz, dtype, e)
     assert np.all(np.abs(gD - rD) <= barD) and np.all(np.abs(gL - rL) <= barL), (nz, dtype)
+
+
+@pytest.mark.parametrize("ny", [1, 17, 100, 512, 513])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f32fast"])
+@pytest.mark.parametrize("nx", [5, 8])
+def test_reverse_step_y_sweep_with_the_x_tile_in_lds(nx, ny, dtype):
+    # the transposed y sweep of the reverse step forms its parameter sums
+    # from the recomputed x, which k_adj_tr_tile fetches into LDS while it
+    # solves (y lines of up to 512 voxels, rows of whole 16-byte chunks: nx =
+    # 8 gives 16 values per row in every storage form, nx = 5 gives 10, FP64
+    # only); elsewhere the strided kernel reads x after its solve.  Both
+    # against the oracle's adjoint: the gradient at the storage form's bar,
+    # dL/dD and dL/dlambda within their normwise bars
+    import torch
+    from torch.profiler import ProfilerActivity, profile
+    from gpu_helpers import oracle_adjoint, param_grad_bars
+    p = small_problem((nx, ny, 6), 2, seed=830 + ny + nx, nsrc=30, ndir=8)
+    p.dtype = dtype
+    rng = np.random.default_rng(ny + 7 * nx)
+    gin = (rng.random(p.shape) - 0.5).astype(np.float64 if dtype == "f64" else np.float32)
+    g = make_grid(p, dtype)
+    u = upload(p, g)
+    gg = torch.from_numpy(gin.copy()).cuda()
+    torch.cuda.synchronize()
+    with profile(activities=[ProfilerActivity.CUDA]) as prof:
+        gD, gL = g.step_adjoint(u, gg)
+        torch.cuda.synchronize()
+    names = {e.name for e in prof.events()}
+    state = g.read_field(u)
+    g.close()
+    tile = ny <= 512 and (nx * 2) % (2 if dtype == "f64" else 4) == 0
+    # k_adj_tr_tile<T, C, M, COEF, XROWS>: the y lines' form ends in "false>"
+    assert any("k_adj_tr_tile" in n and n.split("(")[0].rstrip().endswith("false>") for n in names) == tile, \
+        sorted(names)
+    rg, rD, rL = oracle_adjoint(p, state, gin)
+    barD, barL = param_grad_bars(p, state, gin)
+    e = rel_err(gg.double().cpu().numpy(), rg)[0]
+    assert e <= {"f64": 1e-12, "f32": 1e-5, "f32fast": 1e-5}[dtype], (nx, ny, dtype, e)
+    assert np.all(np.abs(gD - rD) <= barD) and np.all(np.abs(gL - rL) <= barL), (nx, ny, dtype)
+
+
+@pytest.mark.parametrize("nx", [17, 100, 300, 512, 513])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f32fast"])
+@pytest.mark.parametrize("S", [2, 4])
+def test_reverse_step_x_sweep_with_the_x_tile_in_lds(S, nx, dtype):
+    # the transposed x sweep through x rows (plan kind 3) forms its sums with
+    # the recomputed x fetched into LDS (k_adj_tr_tile) where a 16-byte chunk
+    # holds whole substrates of one row: S = 4 in every storage form, S = 2 in
+    # FP64; other x plans (row tiles) keep their own kernels.  Against the
+    # oracle's adjoint at the usual bars
+    import torch
+    from torch.profiler import ProfilerActivity, profile
+    from gpu_helpers import oracle_adjoint, param_grad_bars
+    p = small_problem((nx, 3, 4), S, seed=850 + nx + S, nsrc=30, ndir=8)
+    p.dtype = dtype
+    rng = np.random.default_rng(nx + 5 * S)
+    gin = (rng.random(p.shape) - 0.5).astype(np.float64 if dtype == "f64" else np.float32)
+    g = make_grid(p, dtype)
+    kind = g.get_plan(0)[0]
+    u = upload(p, g)
+    gg = torch.from_numpy(gin.copy()).cuda()
+    torch.cuda.synchronize()
+    with profile(activities=[ProfilerActivity.CUDA]) as prof:
+        gD, gL = g.step_adjoint(u, gg)
+        torch.cuda.synchronize()
+    names = {e.name for e in prof.events()}
+    state = g.read_field(u)
+    g.close()
+    per_chunk = 2 if dtype == "f64" else 4
+    tile = kind == 3 and nx <= 512 and S % per_chunk == 0
+    assert any("k_adj_tr_tile" in n and n.split("(")[0].rstrip().endswith("true>") for n in names) == tile, \
+        (kind, sorted(names))
+    rg, rD, rL = oracle_adjoint(p, state, gin)
+    barD, barL = param_grad_bars(p, state, gin)
+    e = rel_err(gg.double().cpu().numpy(), rg)[0]
+    assert e <= {"f64": 1e-12, "f32": 1e-5, "f32fast": 1e-5}[dtype], (S, nx, dtype, e)
+    assert np.all(np.abs(gD - rD) <= barD) and np.all(np.abs(gL - rL) <= barL), (S, nx, dtype)

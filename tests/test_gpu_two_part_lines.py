@@ -114,7 +114,9 @@ def test_two_part_plan_runs_its_own_kernel(dtype):
     # the forward sweep of a kind-5 axis launches the two-part kernel (not
     # the kind-1 plan it falls back to), its transposed sweep the kind-1
     # kernel (the reverse step's forward recomputation runs the two-part
-    # kernel again); kernel names as the profiler records them
+    # kernel again); kernel names as the profiler records them.  Rows of 21
+    # values are not whole 16-byte chunks, so the reverse step's y sweep is
+    # not the LDS-tile form (k_adj_tr_tile)
     import torch
     from torch.profiler import ProfilerActivity, profile
     p = small_problem((7, 100, 5), 3, seed=751, nsrc=10, nsteps=1)
