@@ -210,6 +210,44 @@ __device__ __forceinline__ void load_lds16(const void* src, void* wave_base)
     __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)wave_base, 16, 0, 0);
 }
 
+// The block's tile [K*M planes][lpw lines] of T (lines of its tile
+// contiguous, planes st apart; K*M*lpw = 512*M, the block's 512 threads
+// times M) into LDS at gb with 16-byte global-to-LDS loads, which take no
+// registers: chunk c = plane * lpw/E + part of the plane's row (E = 16 /
+// sizeof(T) values), Q = M * sizeof(T) / 16 chunks per thread, a wave's
+// instruction filling 64 consecutive ones (lane l at 16 * l bytes past its
+// base).  Every lane issues every load:
+// planes past the line end and chunks past the last line read a clamped
+// chunk, so the count in flight is fixed and a later wait for values loaded
+// before these counts them exactly.  Tile line l (a multiple of E) starts at
+// src0 + lineoff(l) at plane 0, its E lines contiguous; nlines = lines from
+// the tile's first to the last line of the grid (at least E, a multiple of
+// E).  The tile is complete once the wave's memory counter is 0 and then,
+// for every wave's part, after a barrier.
+template <typename T, int M, typename F>
+__device__ __forceinline__ void fetch_tile_lds(T* gb, const T* src0, F lineoff, int64_t st, int n, int lpw,
+                                               int64_t nlines)
+{
+    constexpr int E = 16 / (int)sizeof(T);
+    constexpr int Q = M * (int)sizeof(T) / 16;
+    static_assert(Q * 16 == M * (int)sizeof(T), "whole chunks per thread");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int chs = __builtin_ctz((unsigned)(lpw / E));   // chunks per row: a power of two
+    const int64_t cmax = nlines / E - 1;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int j = (q * (int)(blockDim.x >> 6) + wave) * 64;
+        const int c = j + lane;
+        const int pl = min(c >> chs, n - 1);
+        const int cc = (int)min((int64_t)(c & ((1 << chs) - 1)), cmax);
+        load_lds16(src0 + lineoff(cc * E) + pl * st, gb + (int64_t)j * E);
+    }
+}
+
+// vmcnt(0) alone: the wave's vector-memory loads (and global-to-LDS loads)
+// are complete
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // The three register phases of a segment.
 // forward pass with zero carry; G = product of the forward coefficients
 template <typename C, int M, bool TR, typename Coef>
@@ -294,14 +332,13 @@ __device__ __forceinline__ void seg_last(C (&v)[M], C r, const Coef& coef, C X)
 // UNR: see carry_scan (fewer registers for the leader scan where a kernel
 // holds more than one segment's values).  ASYNC: the block has
 // global-to-LDS loads in flight during the solve; its barriers order LDS
-// only (lds_sync), and the backward terms reuse the forward arrays (2
-// arrays instead of 4; leader scan only): every thread reads its own
+// only (lds_sync), and with the leader scan the backward terms reuse the
+// forward arrays (2 arrays instead of 4): every thread reads its own
 // forward carry before it writes its own backward term.
 template <typename C, int M, bool TR, bool PAR, typename Coef, int UNR = 8, bool ASYNC = false>
 __device__ __forceinline__ void solve_segment(C (&v)[M], int seg, int K, int line, int nl, C r,
                                               const Coef& coef, C* sc, bool writer)
 {
-    static_assert(!(ASYNC && PAR), "two carry arrays with the leader scan only");
     auto sync = [] {
         if constexpr (ASYNC) lds_sync();
         else __syncthreads();
@@ -310,8 +347,8 @@ __device__ __forceinline__ void solve_segment(C (&v)[M], int seg, int K, int lin
     const int A = KP ? nl * (KP + 1) : K * nl;
     C* sF = sc;
     C* sG = sc + A;
-    C* sB = ASYNC ? sF : sc + 2 * A;
-    C* sH = ASYNC ? sG : sc + 3 * A;
+    C* sB = ASYNC && !PAR ? sF : sc + 2 * A;
+    C* sH = ASYNC && !PAR ? sG : sc + 3 * A;
     const int slot = KP ? line * (KP + 1) + seg : seg * nl + line;
     C f, G;
     seg_forward<C, M, TR>(v, r, coef, f, G);

@@ -331,41 +331,6 @@ __device__ __forceinline__ void store_seg(const C (&v)[M], T* gp, int64_t st, in
     }
 }
 
-// The block's tile [K*M planes][lpw lines] of T (lines of its tile
-// contiguous, planes st apart) into LDS at gb with 16-byte global-to-LDS
-// loads, which take no registers: chunk c = plane * lpw/E + part of the
-// plane's row (E = 16 / sizeof(T) values), 512 * sizeof(T) chunks, sizeof(T)
-// per thread of the 512, a wave's instruction filling 64 consecutive ones
-// (lane l at 16 * l bytes past its base).  Every lane issues every load:
-// planes past the line end and chunks past the last line read a clamped
-// chunk, so the count in flight is fixed and a later wait for values loaded
-// before these counts them exactly.  Tile line l (a multiple of E) starts at
-// src0 + lineoff(l) at plane 0, its E lines contiguous; nlines = lines from
-// the tile's first to the last line of the grid (at least E, a multiple of
-// E).  The tile is complete once the wave's memory counter is 0 and then,
-// for every wave's part, after a barrier.
-template <typename T, typename F>
-__device__ __forceinline__ void fetch_tile_lds(T* gb, const T* src0, F lineoff, int64_t st, int n, int lpw,
-                                               int64_t nlines)
-{
-    constexpr int E = 16 / (int)sizeof(T);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int chs = __builtin_ctz((unsigned)(lpw / E));   // chunks per row: a power of two
-    const int64_t cmax = nlines / E - 1;
-#pragma unroll
-    for (int q = 0; q < (int)sizeof(T); ++q) {
-        const int j = (q * (int)(blockDim.x >> 6) + wave) * 64;
-        const int c = j + lane;
-        const int pl = min(c >> chs, n - 1);
-        const int cc = (int)min((int64_t)(c & ((1 << chs) - 1)), cmax);
-        load_lds16(src0 + lineoff(cc * E) + pl * st, gb + (int64_t)j * E);
-    }
-}
-
-// vmcnt(0) alone: the wave's vector-memory loads (and global-to-LDS loads)
-// are complete
-__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
-
 // ------------------------------- reverse step: z recomputation + z transposed
 //
 // The z axis of the reverse step in one pass.  The reverse step needs the
@@ -431,7 +396,7 @@ __global__ __launch_bounds__(512, 4) void k_adj_z_fused(const T* zin, T* grad, A
             // the x values first (the compiler's own wait before their use
             // would otherwise count the tile's loads too)
             wait_vm();
-            fetch_tile_lds<T>(gb, grad + (g.o0 + (int64_t)by) * g.outer_stride + g.p0 + p_first,
+            fetch_tile_lds<T, M>(gb, grad + (g.o0 + (int64_t)by) * g.outer_stride + g.p0 + p_first,
                               [](int l) { return (int64_t)l; }, st, (int)g.n, lpw, g.inner - p_first);
         }
         solve_segment<C, M, false, false, Cf, UNR, DMA>(x, seg, K, line, lpw, r, coef, sc, true);
@@ -557,13 +522,13 @@ __global__ __launch_bounds__(512, 4) void k_adj_tr_tile(const T* in, T* out, Axi
         using Cf = std::decay_t<decltype(coef)>;
         wait_vm();   // the gradient values first, then the x tile in flight
         if constexpr (XROWS)
-            fetch_tile_lds<T>(gb, xf + row0, [&](int l) {
+            fetch_tile_lds<T, M>(gb, xf + row0, [&](int l) {
                 const int r = (int)divS.div((uint32_t)l);
                 return (int64_t)r * nS + (l - r * S);
             }, st,
                               (int)g.n, lpw, g.inner - p_first);
         else
-            fetch_tile_lds<T>(gb, xf + row0, [](int l) { return (int64_t)l; }, st, (int)g.n, lpw, g.inner - p_first);
+            fetch_tile_lds<T, M>(gb, xf + row0, [](int l) { return (int64_t)l; }, st, (int)g.n, lpw, g.inner - p_first);
         solve_segment<C, M, true, false, Cf, 8, true>(y, seg, K, line, lpw, r, coef, sc, true);
     };
     if constexpr (COEF == 1) {
