@@ -56,11 +56,13 @@ def _loss_gpu(p, target, nsteps, D, lam):
 # state itself, out of place; the x kernel follows the default plan: row
 # lines (3 substrates), LDS row tiles (2 substrates, 96 voxels) and pipelined
 # row tiles (2 substrates, 400 voxels).  Axes of one voxel (no neighbours:
-# L_N x = 0 there) close the list.
+# L_N x = 0 there) and 300 substrates (more than the 256 threads of the line
+# sums' blocks: each thread then adds whole substrates) close the list.
 @pytest.mark.parametrize("shape,S,nsrc,ndir", [((21, 17, 13), 3, 80, 12), ((21, 17, 13), 3, 80, 0),
                                                ((21, 17, 13), 3, 0, 12), ((21, 17, 13), 3, 0, 0),
                                                ((96, 9, 7), 2, 0, 0), ((400, 5, 4), 2, 0, 0),
-                                               ((1, 5, 7), 2, 3, 2), ((9, 1, 1), 3, 0, 0)])
+                                               ((1, 5, 7), 2, 3, 2), ((9, 1, 1), 3, 0, 0),
+                                               ((6, 5, 4), 300, 20, 3)])
 def test_adjoint_step_matches_oracle(shape, S, nsrc, ndir):
     import torch
     p = small_problem(shape, S, seed=800, nsrc=nsrc, ndir=ndir)
