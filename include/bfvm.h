@@ -165,8 +165,14 @@ int bfvm_xslab_backward(bfvm_grid g, void* slab, int64_t x0, int64_t x1, int64_t
  * sweep transpose is a transposed Thomas solve (A = L U, solve U^T then L^T),
  * and accumulates per substrate -y^T (L_N x) (w.r.t. r) and -y^T x (w.r.t.
  * beta) with L_N the zero-flux Laplacian: each transposed sweep forms the
- * sums of its lines from the y it holds and the recomputed x, then one
- * launch adds the lines of each substrate in a fixed order (deterministic).
+ * sums of its lines from the y it holds and the recomputed x, then two
+ * launches add the lines of each substrate in a fixed order (chunks of
+ * lines, then the chunks: deterministic).  Lines of up to 512 voxels whose
+ * tile rows are whole, 16-byte aligned chunks (z; y on plan kinds 1 and 5;
+ * x on kind 3 with nsub a multiple of the values per chunk) run a fixed
+ * tile shape, 16 values per thread in 512-thread tiles, whatever the axis's
+ * plan: z recomputed and transposed in one pass, y and x with the
+ * recomputed x fetched into LDS during the solve.
  * Synchronises the stream before returning.
  * Errors: EINVAL, ESTATE, ENOMEM, EDEVICE. */
 int bfvm_step_adjoint(bfvm_grid g, const void* field_in, void* grad,
