@@ -81,11 +81,17 @@ __global__ __launch_bounds__(1024) void k_xslab(T* slab, int m, int S, int64_t l
     const int i0 = seg * M - shift;                         // slab position of slot 0 of the segment
     const int64_t rowbase = row * (int64_t)m * S + s;
     C v[M];
+    // the loads at a raised wave priority, so that a wave loading its tile
+    // is not held behind another block's solve on its SIMD (125-voxel slab
+    // of the 1000^3 x 4 FP64 cube: 3.40 -> 3.29 ms; the batched tiles were
+    // 2% slower with it, the headline z sweep 2% faster)
+    __builtin_amdgcn_s_setprio(2);
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         const int i = std::min(std::max(i0 + k, 0), m - 1);   // padding: clamped, in bounds
         v[k] = (C)slab[rowbase + (int64_t)i * S];
     }
+    __builtin_amdgcn_s_setprio(0);
     stage_window<C, M>(tab, invd, x0, m, S, K, SPw, shift);
     __syncthreads();
     const LdsCoef<C> coef{tab + s * SPw + seg * (M + 1), (C)0};
