@@ -216,14 +216,14 @@ __device__ __forceinline__ void load_lds16(const void* src, void* wave_base)
 // registers: chunk c = plane * lpw/E + part of the plane's row (E = 16 /
 // sizeof(T) values), Q = M * sizeof(T) / 16 chunks per thread, a wave's
 // instruction filling 64 consecutive ones (lane l at 16 * l bytes past its
-// base).  Every lane issues every load:
-// planes past the line end and chunks past the last line read a clamped
-// chunk, so the count in flight is fixed and a later wait for values loaded
-// before these counts them exactly.  Tile line l (a multiple of E) starts at
-// src0 + lineoff(l) at plane 0, its E lines contiguous; nlines = lines from
-// the tile's first to the last line of the grid (at least E, a multiple of
-// E).  The tile is complete once the wave's memory counter is 0 and then,
-// for every wave's part, after a barrier.
+// base).  Every lane issues every load: planes past the line end and chunks
+// past the last line read a clamped chunk, so the count in flight is fixed
+// and a later wait for values loaded before these counts them exactly.
+// Tile line l (a multiple of E) starts at src0 + lineoff(l) at plane 0, its
+// E lines contiguous; nlines = lines from the tile's first to the last line
+// of the grid (at least E, a multiple of E).  The tile is complete once the
+// wave's memory counter is 0 and then, for every wave's part, after a
+// barrier.
 template <typename T, int M, typename F>
 __device__ __forceinline__ void fetch_tile_lds(T* gb, const T* src0, F lineoff, int64_t st, int n, int lpw,
                                                int64_t nlines)
