@@ -257,14 +257,16 @@ __global__ __launch_bounds__(1024) void k_sweep_seg_strided(const T* in, T* out,
     // grid: z 3% faster; y 4% slower, FP32 and the x rows (whose loads reuse
     // cache lines across k) slower, so only this case uses it.
     constexpr bool NT = sizeof(T) == 8 && AX == 2;
-    // The same FP64 z tiles run at a raised wave priority, highest while
-    // they issue their loads, one lower through the solve and back to the
-    // lowest for the stores, so that a wave loading its tile is not held
-    // behind the other block's solve: 1000^3 x 4 FP64 z 12.80 -> 12.56 ms
-    // (loads alone raised) -> 12.43-12.46 ms.  Raised through the stores as
-    // well, z took 14.1 ms; for y and x the raised loads cost 1%, for FP32 z
-    // 1-3%.
-    if constexpr (NT) __builtin_amdgcn_s_setprio(2);
+    // z tiles run at a raised wave priority, highest while they issue their
+    // loads, one lower through the solve and back to the lowest for the
+    // stores, so that a wave loading its tile is not held behind the other
+    // block's solve.  1000^3 x 4: FP64 z 12.80 -> 12.56 ms with the loads
+    // alone raised, 12.43-12.46 ms so; FP32 storage z 7.89 -> 7.69 ms, FP32
+    // arithmetic 6.97 -> 6.73 ms (1-3% slower with the loads alone raised).
+    // Raised through the stores as well, FP64 z took 14.1 ms; for y and x
+    // the raised loads cost 1%.
+    constexpr bool PRI = AX == 2;
+    if constexpr (PRI) __builtin_amdgcn_s_setprio(2);
     if (NT) {
 #pragma unroll
         for (int k = 0; k < M; ++k) v[k] = (C)__builtin_nontemporal_load(&in[base + (k <= last ? k : last) * st]);
@@ -272,7 +274,7 @@ __global__ __launch_bounds__(1024) void k_sweep_seg_strided(const T* in, T* out,
 #pragma unroll
         for (int k = 0; k < M; ++k) v[k] = (C)in[base + (k <= last ? k : last) * st];
     }
-    if constexpr (NT) __builtin_amdgcn_s_setprio(1);
+    if constexpr (PRI) __builtin_amdgcn_s_setprio(1);
     const C r = rr[s];
     const C prev = (TR && i0 > 0 && last >= 0) ? invd[(i0 - 1) * S + s] : (C)0;
     if (COEF == 1) {
@@ -294,7 +296,7 @@ __global__ __launch_bounds__(1024) void k_sweep_seg_strided(const T* in, T* out,
     // here instead of keeping the load addresses live through the solve.
     T* op = out + base;
     asm volatile("" : "+v"(op));
-    if constexpr (NT) __builtin_amdgcn_s_setprio(0);
+    if constexpr (PRI) __builtin_amdgcn_s_setprio(0);
     if (NT) {
         if (cnt == M) {
 #pragma unroll
