@@ -42,8 +42,9 @@ block hand-offs as events, against the whole-line x sweep of the cube.
 
 Fields are placed by the library (bfvm_field_alloc): the sweeps' rate depends
 on where a field's allocation lands in device memory, so --placement-candidates
-allocations (default 4) are timed on one sweep set each and the fastest is
-kept; the line reports every candidate and the step on a plain allocation.
+allocations (default 8; the library takes as many as leave a sixteenth of the
+device free) are timed on one sweep set each and the fastest is kept; the
+line reports every candidate and the step on a plain allocation.
 
 Prints ONE JSON line: voxel-substrate updates/s per LOD step, the roofline
 of the dominant kernel (algorithmic HBM bytes per launch / its mean launch
@@ -92,7 +93,7 @@ def parse():
     ap.add_argument("--cpu-sample-steps", type=int, default=10)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 4 GiB buffer twice (reference for FETCH_SIZE / WRITE_SIZE counters)")
-    ap.add_argument("--placement-candidates", type=int, default=4,
+    ap.add_argument("--placement-candidates", type=int, default=8,
                     help="allocations the library times to place each field (1: a plain allocation)")
     ap.add_argument("--one-part-plans", action="store_true",
                     help="liver12/liver16: run kind-5 axes as the one-part plan of twice the segments")
