@@ -522,8 +522,9 @@ def run_adjoint(args):
                    "grid": [p.nx, p.ny, p.nz], "substrates": p.S},
         "roofline": {"bound": "hbm", "achieved": r64["reverse_step_alg_GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(r64["reverse_step_alg_GBps"] / HBM_PEAK_GBPS, 4), "traffic": None,
-                     "scope": "whole reverse step: 15 element moves per voxel-substrate / step time; the 34 MB "
-                              "field fits the 256 MB memory-side cache, so this can exceed HBM bandwidth",
+                     "scope": f"whole reverse step: {ADJOINT_ELEMS_MOVED} element moves per voxel-substrate / "
+                              "step time; the 34 MB field fits the 256 MB memory-side cache, so this can exceed "
+                              "HBM bandwidth",
                      "algorithmic_bytes_per_step": ADJOINT_ELEMS_MOVED * 8 * upd},
         "adjoint": out,
         "reverse_step_hbm_bound": hbm_bound,
