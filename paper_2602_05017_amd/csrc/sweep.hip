@@ -263,9 +263,10 @@ __global__ __launch_bounds__(1024) void k_sweep_seg_strided(const T* in, T* out,
     // block's solve.  1000^3 x 4: FP64 z 12.80 -> 12.56 ms with the loads
     // alone raised, 12.43-12.46 ms so; FP32 storage z 7.89 -> 7.69 ms, FP32
     // arithmetic 6.97 -> 6.73 ms (1-3% slower with the loads alone raised).
-    // Raised through the stores as well, FP64 z took 14.1 ms; for y and x
-    // the raised loads cost 1%.
-    constexpr bool PRI = AX == 2;
+    // Raised through the stores as well, FP64 z took 14.1 ms.  y with FP32
+    // arithmetic (32-line tiles) gains too: 5.65-5.75 -> 5.32-5.48 ms; FP64 y
+    // and x lost 1-2.5%, FP32-storage y in 16-line tiles 10%.
+    constexpr bool PRI = AX == 2 || (AX == 1 && sizeof(C) == 4);
     if constexpr (PRI) __builtin_amdgcn_s_setprio(2);
     if (NT) {
 #pragma unroll
@@ -1349,12 +1350,13 @@ SweepPlan default_plan(int axis, const AxisGeom& g, int dtype)
         if (check_plan(c, g, dtype).empty() && halves_lds(K, 16, K0, 32, es, cs, ctab) <= (size_t)max_lds() / 2)
             return c;
     }
-    // FP32 y lines on long axes: 32-line tiles (a full 128-byte line per
-    // row) measured 2-3% faster than 16-line tiles on 1000^3 x 4; FP32 z
-    // with FP64 arithmetic and FP64 lines keep 16-line tiles (z was 15%
-    // slower with 32).  With FP32 arithmetic (half the registers) z takes
-    // 32-line tiles too: 7.66 -> 7.00 ms on 1000^3 x 4.
-    if (es == 4 && (axis == 1 || cs == 4) && g.n >= 512) {
+    // FP32 arithmetic on long y and z lines: 32-line tiles (a full 128-byte
+    // line per row; with FP32 registers the 1024-thread tile still leaves
+    // room for its waves): z 7.66 -> 7.00 ms on 1000^3 x 4, y faster too.
+    // FP32 storage with FP64 arithmetic keeps 16-line tiles (two 512-thread
+    // blocks per CU): y 7.17-7.21 ms with 32 lines, 6.16-6.17 ms with 16 on
+    // 1000^3 x 4 (z was 15% slower with 32); FP64 lines keep 16 as well.
+    if (es == 4 && cs == 4 && g.n >= 512) {
         SweepPlan c;
         c.kind = PLAN_SEG_STRIDED;
         c.m = 32;

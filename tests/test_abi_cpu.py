@@ -133,11 +133,12 @@ def test_default_plans_are_valid(L, shape, dtype):
     L.bfvm_destroy(g)
 
 
-def test_long_fp32_y_lines_use_full_cache_line_tiles(L):
-    # FP32 y lines of 1000 take 32-line tiles (128 bytes per row), and so do
-    # z lines with FP32 arithmetic; FP64 keeps 16.  FP32 rows go through the
-    # pipelined row tiles, two rows per tile.
-    for dtype, x, y, z in ((1, (4, 16, 8, 2), (1, 32, 16, 32), (1, 32, 8, 16)),
+def test_long_fp32_arithmetic_lines_use_full_cache_line_tiles(L):
+    # y and z lines of 1000 with FP32 arithmetic take 32-line tiles (128
+    # bytes per row); FP32 storage with FP64 arithmetic and FP64 keep 16
+    # (two 512-thread blocks per CU).  FP32 rows go through the pipelined
+    # row tiles, two rows per tile.
+    for dtype, x, y, z in ((1, (4, 16, 8, 2), (1, 32, 8, 16), (1, 32, 8, 16)),
                            (2, (4, 16, 8, 2), (1, 32, 16, 32), (1, 32, 16, 32)),
                            (0, (3, 32, 8, 16), (1, 32, 8, 16), (1, 32, 8, 16))):
         st, g = _create(L, 1000, 1000, 1000, 4, dtype=dtype)
