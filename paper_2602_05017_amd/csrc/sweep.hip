@@ -1061,7 +1061,11 @@ __global__ __launch_bounds__(512) void k_sweep_seg_xpipe(const T* in, T* out, Ax
         C v[M];
 #pragma unroll
         for (int k = 0; k < M; ++k) v[k] = (C)my[(k <= last ? k : last) * S];
-        solve_segment<C, M, TR, true>(v, j, K, active ? rw * S + s : 0, nl, r, coef, sc, active);
+        // LDS-only barriers in the solve: the next tile's loads above stay in
+        // flight through it instead of being waited for at its first barrier
+        // (1000^3 x 4 FP32 storage x 6.60 -> 6.50 ms)
+        solve_segment<C, M, TR, true, RegCoef<C, M>, 8, true>(v, j, K, active ? rw * S + s : 0, nl, r, coef, sc,
+                                                              active);
         if (cnt == M) {
 #pragma unroll
             for (int k = 0; k < M; ++k) my[k * S] = (T)v[k];
